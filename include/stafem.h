@@ -1,0 +1,159 @@
+/*
+ * stafem.h -- C ABI of libstafem.so: exact streaming assembly of the implicit
+ * system matrix A_t = M_t + dt^2 K_t over a preallocated superset tet mesh,
+ * on one AMD MI355X (gfx950).
+ *
+ * The method (Acharya & Hyde, "STA-FEM: Exact Streaming Assembly for
+ * Preplanned Dynamic Tetrahedral Topology Edits"):
+ *   - Sec. 3.1 / Sec. 3.3: a fixed superset of vertices and candidate tets, an
+ *     active mask over the candidates, and per-frame edit sets of deleted and
+ *     added tets (eqs. (5), (6)).
+ *   - Sec. 3.4 eq. (8): A_t = sum over active tets tau of P_tau^T A_tau P_tau,
+ *     here with A_tau = dt^2 K_tau + M_tau (the implicit-Euler matrix of
+ *     Sec. 6.2 eq. (9)), K_tau the 12x12 P1 linear-elasticity stiffness and
+ *     M_tau the lumped mass, and eps = 0.
+ *   - Sec. 3.3 invariant: after every frame the maintained matrix equals a
+ *     rebuild from scratch on the current active set.  Here "equals" is
+ *     bitwise in IEEE binary64: every entry is the sum of its active element
+ *     terms in ascending element id starting from +0.0, whether it comes from
+ *     sta_full_rebuild or from sta_apply_edits.
+ *   - Sec. 3.5: full_rebuild and the streaming update are the policies; the
+ *     streaming update touches only entries covered by edited tets.
+ *
+ * Matrix layout (values are owned by the context, in HBM):
+ *   CSR over 3n rows, int32 indices.  Row 3i+p is displacement component p of
+ *   node i.  Row 3i+p holds columns 3j+q for every node j that shares a
+ *   candidate tet with i (j = i included), ascending.  The pattern is that of
+ *   the whole superset and never changes; entries with no active incident tet
+ *   hold +0.0.  A node in no candidate tet has empty rows.
+ *
+ * Element arithmetic (fixed so results are reproducible bit for bit): for a
+ * tet with vertices x0..x3 in its given order, d_k = x_k - x_0,
+ * c1 = d2 x d3, c2 = d3 x d1, c3 = d1 x d2, det = d1 . c1,
+ * g_k = c_k * (1/det), g_0 = -((g_1 + g_2) + g_3), V = |det| / 6,
+ * lamV = (E*cl*V)*dt^2, muV = (E*cm*V)*dt^2 with cl = nu/((1+nu)(1-2nu)),
+ * cm = 0.5/(1+nu), m = (rho*V)*0.25, and
+ *   A[3a+i][3b+j] = lamV*(g_ai*g_bj) + muV*(g_aj*g_bi) [+ muV*(g_a.g_b) if i=j]
+ *                   [+ m if a=b and i=j],
+ * each operation rounded once, left to right, no fused multiply-add.
+ *
+ * Streams: every call that takes `stream` (a hipStream_t, NULL = default
+ * stream) only enqueues work on it and returns without waiting, unless
+ * documented as synchronising.  Results are visible to later work on the
+ * same stream.
+ *
+ * Errors: functions return a sta_status (0 = STA_OK, negative = error).
+ * Host-checkable errors return before anything is modified.  Errors that
+ * only the device can see (edit ids held in device memory) are recorded in
+ * the context; the affected frame is rolled back (mask and values unchanged)
+ * and sta_status_sync reports the error.  sta_last_error gives a message.
+ * No function throws.
+ *
+ * Threading: a context may be used by one host thread at a time.  Calls on
+ * one context must be ordered on one stream (or synchronised by the caller).
+ */
+#ifndef STAFEM_H
+#define STAFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sta_ctx sta_ctx;
+typedef int sta_status;
+
+#define STA_OK 0
+#define STA_EINVAL (-1)       /* bad argument (null pointer, size, material) */
+#define STA_ENOMEM (-2)       /* device or host allocation failed */
+#define STA_EHIP (-3)         /* a HIP runtime call failed */
+#define STA_EDEGENERATE (-4)  /* a candidate tet has det == 0 or a repeated node */
+#define STA_ESTALE (-5)       /* parameters changed; call sta_full_rebuild first */
+#define STA_ERANGE (-6)       /* an edit id is outside [0, n_tets) or a state is not 0/1 */
+#define STA_EDUP (-7)         /* an edit list names the same tet twice */
+
+/* Build the superset pattern and the initial matrix (Sec. 3.1 inputs:
+ * vertices, candidate pool, initial mask; Alg. 1 initialisation).
+ *   x      host, n_nodes*3 float64, row-major (x, y, z per node)
+ *   tets   host, n_tets*4 int32, vertex ids in [0, n_nodes), 4 distinct
+ *   E      host, n_tets float64 Young's modulus per candidate
+ *   nu, rho, dt  Poisson ratio in (-1, 0.5), density >= 0, time step > 0
+ *   mask0  host, n_tets uint8 in {0, 1}
+ * Inputs are copied; the caller keeps ownership.  Synchronises `stream`.
+ * On success *out owns all device memory until sta_destroy; values hold
+ * rebuild(mask0).  Element matrices are computed for every candidate here, so
+ * later activations need no recomputation unless parameters change.
+ * Errors: STA_EINVAL, STA_EDEGENERATE, STA_ENOMEM, STA_EHIP; *out = NULL. */
+sta_status sta_build_pattern(const double* x, int64_t n_nodes, const int32_t* tets, int64_t n_tets,
+                             const double* E, double nu, double rho, double dt,
+                             const uint8_t* mask0, void* stream, sta_ctx** out);
+
+/* Policy full_rebuild (Sec. 3.5): recompute the element matrices of every
+ * active tet and re-sum every entry of A from the current mask.  Clears
+ * STA_ESTALE.  Asynchronous on `stream`. */
+sta_status sta_full_rebuild(sta_ctx* ctx, void* stream);
+
+/* Streaming update for one frame (Sec. 3.2, Alg. 1): edit k sets tet
+ * ids_dev[k] to state states_dev[k] (1 = add, eq. (6); 0 = delete, eq. (5)).
+ *   ids_dev     device, n_edits int32
+ *   states_dev  device, n_edits uint8
+ * Ids must be distinct within one call (the edits are sets); an edit to the
+ * state a tet already has is allowed and changes nothing.  Only entries
+ * covered by tets whose state changed are recomputed, each from its
+ * incidence list in ascending element id, so the result is bitwise equal to
+ * sta_full_rebuild on the new mask.  Asynchronous on `stream`; the edit
+ * arrays must stay valid until the work completes.  Bad ids / states /
+ * duplicates found on the device roll the whole frame back and are reported
+ * by sta_status_sync.  Host errors: STA_EINVAL (n_edits < 0 or > n_tets),
+ * STA_ESTALE (parameters changed without a rebuild). */
+sta_status sta_apply_edits(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* states_dev,
+                           int64_t n_edits, void* stream);
+
+/* Device pointer to the nnz CSR values (borrowed; valid until sta_destroy,
+ * updated in place; order reads after the producing work on the stream). */
+const double* sta_values_ptr(const sta_ctx* ctx);
+
+/* Copy the nnz values into a caller-owned device buffer (stream-ordered). */
+sta_status sta_copy_values(const sta_ctx* ctx, double* dst_dev, void* stream);
+
+/* Sizes: rows = 3*n_nodes, nnz, diagonal / off-diagonal 3x3 node blocks. */
+sta_status sta_sizes(const sta_ctx* ctx, int64_t* n_rows, int64_t* nnz, int64_t* n_diag_blocks,
+                     int64_t* n_off_blocks);
+
+/* Device pointers to the CSR row pointer (n_rows+1) and column index (nnz)
+ * arrays, and to the active mask (n_tets uint8).  Borrowed. */
+sta_status sta_pattern_ptrs(const sta_ctx* ctx, const int32_t** rowptr_dev, const int32_t** colidx_dev,
+                            const uint8_t** mask_dev);
+
+/* Copy the CSR pattern to host arrays of n_rows+1 and nnz int32.  Synchronous. */
+sta_status sta_pattern_host(const sta_ctx* ctx, int32_t* rowptr, int32_t* colidx);
+
+/* Statistics of the last sta_apply_edits: 3x3 blocks recomputed, matrix
+ * slots written (both triangles counted), incidences read, tets whose state
+ * changed, tets activated.  Synchronises `stream`.  Any pointer may be NULL. */
+sta_status sta_last_frame_stats(sta_ctx* ctx, void* stream, int64_t* touched_blocks, int64_t* touched_slots,
+                                int64_t* touched_incidences, int64_t* changed, int64_t* activated);
+
+/* Replace node positions (device, n_nodes*3 float64 row-major) and Young's
+ * moduli (device, n_tets float64); either may be NULL to keep the current
+ * one.  The matrix is then stale: sta_apply_edits returns STA_ESTALE until
+ * sta_full_rebuild.  Asynchronous on `stream`. */
+sta_status sta_set_params(sta_ctx* ctx, const double* x_dev, const double* E_dev, void* stream);
+
+/* Synchronise `stream`, return and clear the first error the device
+ * recorded (STA_ERANGE, STA_EDUP, STA_EDEGENERATE), else STA_OK. */
+sta_status sta_status_sync(sta_ctx* ctx, void* stream);
+
+/* Message for the last error on this context (or of the last failed
+ * sta_build_pattern when ctx is NULL).  Never NULL. */
+const char* sta_last_error(const sta_ctx* ctx);
+
+/* Free everything the context owns.  NULL is ignored. */
+void sta_destroy(sta_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STAFEM_H */

@@ -1,0 +1,202 @@
+"""Python binding of libstafem.so (the C ABI in include/stafem.h).
+
+Argument marshalling only: every step of the assembly runs in the HIP
+library.  PyTorch supplies device memory for edit lists and results and the
+current HIP stream.  torch is imported before the library is loaded so that
+both bind to the one HIP runtime torch ships (same soname).
+
+There is no CPU fallback: if libstafem.so is missing or no GPU is visible,
+the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libstafem.so")
+
+STATUS = {
+    0: "STA_OK", -1: "STA_EINVAL", -2: "STA_ENOMEM", -3: "STA_EHIP", -4: "STA_EDEGENERATE",
+    -5: "STA_ESTALE", -6: "STA_ERANGE", -7: "STA_EDUP",
+}
+STA_OK, STA_EINVAL, STA_ENOMEM, STA_EHIP, STA_EDEGENERATE, STA_ESTALE, STA_ERANGE, STA_EDUP = 0, -1, -2, -3, -4, -5, -6, -7
+
+
+class StafemError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_dbl = ctypes.c_double
+_int = ctypes.c_int
+
+# name -> (restype, argtypes); mirrors include/stafem.h
+SIGNATURES = {
+    "sta_build_pattern": (_int, [_vp, _i64, _vp, _i64, _vp, _dbl, _dbl, _dbl, _vp, _vp, ctypes.POINTER(_vp)]),
+    "sta_full_rebuild": (_int, [_vp, _vp]),
+    "sta_apply_edits": (_int, [_vp, _vp, _vp, _i64, _vp]),
+    "sta_values_ptr": (_vp, [_vp]),
+    "sta_copy_values": (_int, [_vp, _vp, _vp]),
+    "sta_sizes": (_int, [_vp, _i64p, _i64p, _i64p, _i64p]),
+    "sta_pattern_ptrs": (_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
+    "sta_pattern_host": (_int, [_vp, _vp, _vp]),
+    "sta_last_frame_stats": (_int, [_vp, _vp, _i64p, _i64p, _i64p, _i64p, _i64p]),
+    "sta_set_params": (_int, [_vp, _vp, _vp, _vp]),
+    "sta_status_sync": (_int, [_vp, _vp]),
+    "sta_last_error": (ctypes.c_char_p, [_vp]),
+    "sta_destroy": (None, [_vp]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libstafem.so and declare its signatures; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: run `python -m paper_2605_11673_amd.build`")
+    L = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _stream_handle(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return _vp(s.cuda_stream)
+
+
+def _check(code: int, ctx=None):
+    if code != STA_OK:
+        msg = load().sta_last_error(ctx)
+        raise StafemError(code, msg.decode() if msg else "")
+
+
+def _dev_ptr(t: torch.Tensor) -> _vp:
+    return _vp(t.data_ptr())
+
+
+class Assembler:
+    """One superset mesh: its fixed pattern, element contributions and current A_t.
+
+    x (n, 3) float64, tets (m, 4) int32, E (m,) float64, mask0 (m,) uint8 are
+    host arrays; they are copied into the context.
+    """
+
+    def __init__(self, x, tets, E, nu, rho, dt, mask0, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the HIP assembly path needs an MI355X")
+        L = load()
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        tets = np.ascontiguousarray(tets, dtype=np.int32)
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        mask0 = np.ascontiguousarray(mask0, dtype=np.uint8)
+        self.n_nodes, self.n_tets = int(x.shape[0]), int(tets.shape[0])
+        ctx = _vp()
+        code = L.sta_build_pattern(x.ctypes.data, self.n_nodes, tets.ctypes.data, self.n_tets, E.ctypes.data,
+                                   float(nu), float(rho), float(dt), mask0.ctypes.data,
+                                   _stream_handle(stream), ctypes.byref(ctx))
+        _check(code, None)
+        self._ctx = ctx
+        self.nu, self.rho, self.dt = float(nu), float(rho), float(dt)
+        r, z, d, o = _i64(), _i64(), _i64(), _i64()
+        _check(L.sta_sizes(ctx, ctypes.byref(r), ctypes.byref(z), ctypes.byref(d), ctypes.byref(o)), ctx)
+        self.n_rows, self.nnz, self.n_diag_blocks, self.n_off_blocks = r.value, z.value, d.value, o.value
+
+    @classmethod
+    def from_workload(cls, w, stream=None):
+        return cls(w.x, w.tets, w.E, w.nu, w.rho, w.dt, w.mask0, stream)
+
+    # -- lifetime -------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_ctx", None):
+            load().sta_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._ctx
+
+    # -- the hot path ---------------------------------------------------------
+    def full_rebuild(self, stream=None):
+        _check(load().sta_full_rebuild(self._ctx, _stream_handle(stream)), self._ctx)
+
+    def apply_edits(self, ids: torch.Tensor, states: torch.Tensor, stream=None):
+        """ids: int32 CUDA tensor, states: uint8 CUDA tensor (same length)."""
+        if ids.numel() != states.numel():
+            raise ValueError("ids and states differ in length")
+        if ids.numel() and (ids.dtype != torch.int32 or states.dtype != torch.uint8 or not ids.is_cuda
+                            or not states.is_cuda or not ids.is_contiguous() or not states.is_contiguous()):
+            raise TypeError("ids must be contiguous int32 and states contiguous uint8 CUDA tensors")
+        _check(load().sta_apply_edits(self._ctx, _dev_ptr(ids) if ids.numel() else None,
+                                      _dev_ptr(states) if ids.numel() else None, int(ids.numel()),
+                                      _stream_handle(stream)), self._ctx)
+
+    def values_ptr(self) -> int:
+        return int(load().sta_values_ptr(self._ctx) or 0)
+
+    def values(self, stream=None) -> torch.Tensor:
+        """A copy of the current CSR values (float64 CUDA tensor), stream-ordered."""
+        out = torch.empty(self.nnz, dtype=torch.float64, device="cuda")
+        _check(load().sta_copy_values(self._ctx, _dev_ptr(out), _stream_handle(stream)), self._ctx)
+        return out
+
+    def pattern(self):
+        """(rowptr, colidx) int32 numpy arrays."""
+        rp = np.empty(self.n_rows + 1, dtype=np.int32)
+        ci = np.empty(max(self.nnz, 1), dtype=np.int32)
+        _check(load().sta_pattern_host(self._ctx, rp.ctypes.data, ci.ctypes.data), self._ctx)
+        return rp, ci[: self.nnz]
+
+    def pattern_ptrs(self):
+        rp, ci, mk = _vp(), _vp(), _vp()
+        _check(load().sta_pattern_ptrs(self._ctx, ctypes.byref(rp), ctypes.byref(ci), ctypes.byref(mk)), self._ctx)
+        return rp.value, ci.value, mk.value
+
+    def last_frame_stats(self, stream=None) -> dict:
+        v = [_i64() for _ in range(5)]
+        _check(load().sta_last_frame_stats(self._ctx, _stream_handle(stream), *[ctypes.byref(a) for a in v]),
+               self._ctx)
+        keys = ("touched_blocks", "touched_slots", "touched_incidences", "changed", "activated")
+        return {k: a.value for k, a in zip(keys, v)}
+
+    def set_params(self, x: torch.Tensor | None = None, E: torch.Tensor | None = None, stream=None):
+        """x: (n, 3) float64 CUDA tensor, E: (m,) float64 CUDA tensor; either may be None."""
+        for t in (x, E):
+            if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()):
+                raise TypeError("set_params takes contiguous float64 CUDA tensors")
+        _check(load().sta_set_params(self._ctx, _dev_ptr(x) if x is not None else None,
+                                     _dev_ptr(E) if E is not None else None, _stream_handle(stream)), self._ctx)
+
+    def status_sync(self, stream=None) -> int:
+        """Synchronise and return (and clear) the first device-detected error code."""
+        return int(load().sta_status_sync(self._ctx, _stream_handle(stream)))
+
+    def last_error(self) -> str:
+        m = load().sta_last_error(self._ctx)
+        return m.decode() if m else ""
+
+
+def upload_frame(ids: np.ndarray, states: np.ndarray, device="cuda"):
+    """Host edit arrays -> (int32, uint8) CUDA tensors."""
+    return (torch.from_numpy(np.ascontiguousarray(ids, dtype=np.int32)).to(device),
+            torch.from_numpy(np.ascontiguousarray(states, dtype=np.uint8)).to(device))
