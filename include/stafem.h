@@ -110,6 +110,16 @@ sta_status sta_full_rebuild(sta_ctx* ctx, void* stream);
 sta_status sta_apply_edits(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* states_dev,
                            int64_t n_edits, void* stream);
 
+/* sta_apply_edits with the edit count read on the device: *n_dev (device
+ * int32) edits are taken from ids_dev / states_dev, whose allocations hold
+ * `capacity` entries (1 <= capacity <= n_tets).  Nothing on the host depends
+ * on the count, so the call can be captured once into a HIP graph and the
+ * graph replayed with new edit lists written into the same buffers.
+ * *n_dev outside [0, capacity] is reported as STA_ERANGE by sta_status_sync
+ * and the frame is skipped. */
+sta_status sta_apply_edits_dev(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* states_dev,
+                               const int32_t* n_dev, int64_t capacity, void* stream);
+
 /* Device pointer to the nnz CSR values (borrowed; valid until sta_destroy,
  * updated in place; order reads after the producing work on the stream). */
 const double* sta_values_ptr(const sta_ctx* ctx);
@@ -129,11 +139,31 @@ sta_status sta_pattern_ptrs(const sta_ctx* ctx, const int32_t** rowptr_dev, cons
 /* Copy the CSR pattern to host arrays of n_rows+1 and nnz int32.  Synchronous. */
 sta_status sta_pattern_host(const sta_ctx* ctx, int32_t* rowptr, int32_t* colidx);
 
-/* Statistics of the last sta_apply_edits: 3x3 blocks recomputed, matrix
- * slots written (both triangles counted), incidences read, tets whose state
- * changed, tets activated.  Synchronises `stream`.  Any pointer may be NULL. */
-sta_status sta_last_frame_stats(sta_ctx* ctx, void* stream, int64_t* touched_blocks, int64_t* touched_slots,
-                                int64_t* touched_incidences, int64_t* changed, int64_t* activated);
+/* Statistics of the last sta_apply_edits, written to out[0 .. n_out-1]:
+ *   [0] diagonal 3x3 blocks recomputed   [1] off-diagonal blocks recomputed
+ *   [2] incidences read for [0]          [3] incidences read for [1]
+ *   [4] matrix slots written (both triangles)
+ *   [5] tets whose state changed         [6] of those, tets activated
+ *   [7] edits in the list                [8] 1 if the frame was rolled back
+ * Synchronises `stream`. */
+#define STA_NUM_FRAME_STATS 9
+sta_status sta_last_frame_stats(sta_ctx* ctx, void* stream, int64_t* out, int n_out);
+
+/* Per-kernel timing (tracing aid).  While enabled, every kernel this context
+ * launches is bracketed by two HIP events on the launch stream.
+ * sta_kernel_times synchronises `stream`, writes per kernel id the number of
+ * launches and their summed event-to-event duration in milliseconds (arrays
+ * of STA_NUM_KERNELS), and resets the counters. */
+#define STA_KERNEL_ELEMENT 0   /* element contributions (rebuild / activation) */
+#define STA_KERNEL_REDUCE 1    /* re-sum of every block (rebuild) */
+#define STA_KERNEL_EDITS 2     /* streaming phase 1: validate, flip, claim */
+#define STA_KERNEL_TOUCHED 3   /* streaming phase 2: re-sum claimed blocks */
+#define STA_KERNEL_ADJOINT 4
+#define STA_KERNEL_SOLVE 5     /* all kernels of one CG solve */
+#define STA_KERNEL_BATCH 6     /* fused batched frame */
+#define STA_NUM_KERNELS 8
+sta_status sta_enable_kernel_timing(sta_ctx* ctx, int on);
+sta_status sta_kernel_times(sta_ctx* ctx, void* stream, int64_t* launches, double* ms);
 
 /* Replace node positions (device, n_nodes*3 float64 row-major) and Young's
  * moduli (device, n_tets float64); either may be NULL to keep the current

@@ -80,6 +80,37 @@ Material material(double nu, double rho, double dt)
     return m;
 }
 
+hipEvent_t take_event(sta_ctx* c)
+{
+    if (!c->event_pool.empty()) {
+        hipEvent_t ev = c->event_pool.back();
+        c->event_pool.pop_back();
+        return ev;
+    }
+    hipEvent_t ev = nullptr;
+    if (hipEventCreate(&ev) != hipSuccess)
+        return nullptr;
+    return ev;
+}
+
+// Run one launcher, bracketed by events when kernel timing is on.
+template <class F>
+hipError_t timed(sta_ctx* c, int kernel, hipStream_t s, F&& launch)
+{
+    if (!c->timing)
+        return launch();
+    hipEvent_t a = take_event(c), b = take_event(c);
+    if (!a || !b)
+        return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, s);
+    if (e == hipSuccess)
+        e = launch();
+    if (e == hipSuccess)
+        e = hipEventRecord(b, s);
+    c->timed.push_back({kernel, a, b});
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -135,8 +166,6 @@ sta_status sta_build_pattern(const double* x, int64_t n_nodes, const int32_t* te
     c->nu = nu;
     c->rho = rho;
     c->dt = dt;
-    c->h_dseg = P.dseg;
-    c->h_oseg = P.oseg;
 
     DevView& v = c->v;
     v.n_nodes = (int32_t)n_nodes;
@@ -145,13 +174,13 @@ sta_status sta_build_pattern(const double* x, int64_t n_nodes, const int32_t* te
     v.no = (int32_t)P.no;
     v.mat = material(nu, rho, dt);
 
+    const int64_t nb = P.nd + P.no;
     double *xs, *E_d, *cd, *co, *values;
     int4* T;
-    uint8_t *mask, *undo;
-    int32_t *dseg, *dinc, *oseg, *oinc, *e2b, *e2p, *claims;
-    int2* dmeta;
-    int4* ometa;
-    uint32_t *cver, *estamp, *dstamp, *ostamp;
+    uint8_t *mask, *undo, *wg_err;
+    int32_t *e2b, *e2p;
+    BlockDesc *desc, *rec;
+    uint32_t *estamp, *bstamp;
     Ctl* ctl;
     hipError_t e = hipSuccess;
 #define ALLOC(ptr, count)                                  \
@@ -164,22 +193,16 @@ sta_status sta_build_pattern(const double* x, int64_t n_nodes, const int32_t* te
     ALLOC(c->rowptr, 3 * n_nodes + 1);
     ALLOC(c->colidx, P.nnz);
     ALLOC(values, P.nnz);
-    ALLOC(dseg, P.nd + 1);
-    ALLOC(dinc, 4 * n_tets);
-    ALLOC(dmeta, P.nd);
-    ALLOC(oseg, P.no + 1);
-    ALLOC(oinc, 6 * n_tets);
-    ALLOC(ometa, P.no);
+    ALLOC(desc, nb);
     ALLOC(e2b, 10 * n_tets);
     ALLOC(e2p, 10 * n_tets);
     ALLOC(cd, 24 * n_tets);
     ALLOC(co, 54 * n_tets);
-    ALLOC(cver, n_tets);
     ALLOC(estamp, n_tets);
-    ALLOC(dstamp, P.nd);
-    ALLOC(ostamp, P.no);
-    ALLOC(claims, 10 * n_tets);
+    ALLOC(bstamp, nb);
+    ALLOC(rec, 10 * n_tets);
     ALLOC(undo, n_tets);
+    ALLOC(wg_err, 16 * n_tets / 256 + 2);
     ALLOC(ctl, 1);
 #undef ALLOC
     if (e != hipSuccess) {
@@ -189,7 +212,7 @@ sta_status sta_build_pattern(const double* x, int64_t n_nodes, const int32_t* te
                     std::string("device allocation: ") + hipGetErrorString(e));
     }
 
-    // host-side SoA / int4 staging
+    // host-side SoA / int4 / descriptor staging
     std::vector<double> hx((size_t)3 * n_nodes);
     for (int64_t i = 0; i < n_nodes; ++i)
         for (int k = 0; k < 3; ++k)
@@ -197,12 +220,17 @@ sta_status sta_build_pattern(const double* x, int64_t n_nodes, const int32_t* te
     std::vector<int4> hT((size_t)n_tets);
     for (int64_t t = 0; t < n_tets; ++t)
         hT[t] = make_int4(tets[4 * t], tets[4 * t + 1], tets[4 * t + 2], tets[4 * t + 3]);
-    std::vector<int2> hdm((size_t)P.nd);
+    std::vector<BlockDesc> hd((size_t)nb);
     for (int64_t b = 0; b < P.nd; ++b)
-        hdm[b] = make_int2(P.dmeta[2 * b], P.dmeta[2 * b + 1]);
-    std::vector<int4> hom((size_t)P.no);
-    for (int64_t b = 0; b < P.no; ++b)
-        hom[b] = make_int4(P.ometa[4 * b], P.ometa[4 * b + 1], P.ometa[4 * b + 2], P.ometa[4 * b + 3]);
+        hd[b] = BlockDesc{P.dseg[b], P.dseg[b + 1], P.dmeta[2 * b], P.dmeta[2 * b + 1],
+                          P.dmeta[2 * b], P.dmeta[2 * b + 1], 0, (int32_t)b};
+    for (int64_t o = 0; o < P.no; ++o)
+        hd[P.nd + o] = BlockDesc{P.oseg[o], P.oseg[o + 1], P.ometa[4 * o], P.ometa[4 * o + 1],
+                                 P.ometa[4 * o + 2], P.ometa[4 * o + 3], 1, (int32_t)(P.nd + o)};
+    std::vector<int32_t> he2b(P.e2b);
+    for (int64_t t = 0; t < n_tets; ++t)
+        for (int j = 4; j < 10; ++j)
+            he2b[10 * t + j] += (int32_t)P.nd;
 
     if (e == hipSuccess) e = upload(xs, hx.data(), hx.size(), s);
     if (e == hipSuccess) e = upload(T, hT.data(), hT.size(), s);
@@ -210,18 +238,11 @@ sta_status sta_build_pattern(const double* x, int64_t n_nodes, const int32_t* te
     if (e == hipSuccess) e = upload(mask, mask0, (size_t)n_tets, s);
     if (e == hipSuccess) e = upload(c->rowptr, P.rowptr.data(), P.rowptr.size(), s);
     if (e == hipSuccess) e = upload(c->colidx, P.colidx.data(), P.colidx.size(), s);
-    if (e == hipSuccess) e = upload(dseg, P.dseg.data(), P.dseg.size(), s);
-    if (e == hipSuccess) e = upload(dinc, P.dinc.data(), P.dinc.size(), s);
-    if (e == hipSuccess) e = upload(dmeta, hdm.data(), hdm.size(), s);
-    if (e == hipSuccess) e = upload(oseg, P.oseg.data(), P.oseg.size(), s);
-    if (e == hipSuccess) e = upload(oinc, P.oinc.data(), P.oinc.size(), s);
-    if (e == hipSuccess) e = upload(ometa, hom.data(), hom.size(), s);
-    if (e == hipSuccess) e = upload(e2b, P.e2b.data(), P.e2b.size(), s);
+    if (e == hipSuccess) e = upload(desc, hd.data(), hd.size(), s);
+    if (e == hipSuccess) e = upload(e2b, he2b.data(), he2b.size(), s);
     if (e == hipSuccess) e = upload(e2p, P.e2p.data(), P.e2p.size(), s);
-    if (e == hipSuccess && n_tets > 0) e = hipMemsetAsync(cver, 0, sizeof(uint32_t) * n_tets, s);
     if (e == hipSuccess && n_tets > 0) e = hipMemsetAsync(estamp, 0, sizeof(uint32_t) * n_tets, s);
-    if (e == hipSuccess && P.nd > 0) e = hipMemsetAsync(dstamp, 0, sizeof(uint32_t) * P.nd, s);
-    if (e == hipSuccess && P.no > 0) e = hipMemsetAsync(ostamp, 0, sizeof(uint32_t) * P.no, s);
+    if (e == hipSuccess && nb > 0) e = hipMemsetAsync(bstamp, 0, sizeof(uint32_t) * nb, s);
     if (e == hipSuccess && P.nnz > 0) e = hipMemsetAsync(values, 0, sizeof(double) * P.nnz, s);
     if (e == hipSuccess) e = hipMemsetAsync(ctl, 0, sizeof(Ctl), s);
 
@@ -231,26 +252,20 @@ sta_status sta_build_pattern(const double* x, int64_t n_nodes, const int32_t* te
     v.T = T;
     v.E = E_d;
     v.mask = mask;
-    v.dseg = dseg;
-    v.dinc = dinc;
-    v.dmeta = dmeta;
-    v.oseg = oseg;
-    v.oinc = oinc;
-    v.ometa = ometa;
+    v.desc = desc;
     v.e2b = e2b;
     v.e2p = e2p;
     v.cd = cd;
     v.co = co;
-    v.cver = cver;
     v.values = values;
     v.estamp = estamp;
-    v.dstamp = dstamp;
-    v.ostamp = ostamp;
-    v.claims = claims;
+    v.bstamp = bstamp;
+    v.rec = rec;
     v.undo = undo;
+    v.wg_err = wg_err;
     v.ctl = ctl;
 
-    if (e == hipSuccess) e = launch_element(v, true, c->ver, s);
+    if (e == hipSuccess) e = launch_element(v, s);
     if (e == hipSuccess) e = launch_reduce_all(v, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     int32_t bits = 0;
@@ -274,9 +289,9 @@ sta_status sta_full_rebuild(sta_ctx* ctx, void* stream)
     if (!ctx)
         return STA_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = launch_element(ctx->v, false, ctx->ver, s);
+    hipError_t e = timed(ctx, STA_KERNEL_ELEMENT, s, [&] { return launch_element(ctx->v, s); });
     if (e == hipSuccess)
-        e = launch_reduce_all(ctx->v, s);
+        e = timed(ctx, STA_KERNEL_REDUCE, s, [&] { return launch_reduce_all(ctx->v, s); });
     if (e != hipSuccess)
         return hip_fail(ctx, e, "full_rebuild launch");
     ctx->stale = false;
@@ -294,13 +309,36 @@ sta_status sta_apply_edits(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* 
         return fail(ctx, STA_EINVAL, "NULL edit array");
     if (ctx->stale)
         return fail(ctx, STA_ESTALE, "parameters changed: call sta_full_rebuild before sta_apply_edits");
-    ctx->last_n_edits = n_edits;
-    if (n_edits == 0)
-        return STA_OK;
-    hipError_t e = launch_edits(ctx->v, ids_dev, states_dev, (int32_t)n_edits, ctx->ver,
-                                static_cast<hipStream_t>(stream));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t n = (int32_t)n_edits;
+    hipError_t e = timed(ctx, STA_KERNEL_EDITS, s,
+                         [&] { return launch_edit_phase(ctx->v, ids_dev, states_dev, n, nullptr, s); });
+    if (e == hipSuccess)
+        e = timed(ctx, STA_KERNEL_TOUCHED, s, [&] { return launch_touched_phase(ctx->v, ids_dev, n, nullptr, s); });
     if (e != hipSuccess)
         return hip_fail(ctx, e, "apply_edits launch");
+    return STA_OK;
+}
+
+sta_status sta_apply_edits_dev(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* states_dev, const int32_t* n_dev,
+                               int64_t capacity, void* stream)
+{
+    if (!ctx)
+        return STA_EINVAL;
+    if (capacity < 1 || capacity > ctx->n_tets)
+        return fail(ctx, STA_EINVAL, "capacity must be in [1, n_tets]");
+    if (!ids_dev || !states_dev || !n_dev)
+        return fail(ctx, STA_EINVAL, "NULL edit array or count");
+    if (ctx->stale)
+        return fail(ctx, STA_ESTALE, "parameters changed: call sta_full_rebuild before sta_apply_edits_dev");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t cap = (int32_t)capacity;
+    hipError_t e = timed(ctx, STA_KERNEL_EDITS, s,
+                         [&] { return launch_edit_phase(ctx->v, ids_dev, states_dev, cap, n_dev, s); });
+    if (e == hipSuccess)
+        e = timed(ctx, STA_KERNEL_TOUCHED, s, [&] { return launch_touched_phase(ctx->v, ids_dev, cap, n_dev, s); });
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "apply_edits_dev launch");
     return STA_OK;
 }
 
@@ -356,53 +394,87 @@ sta_status sta_pattern_host(const sta_ctx* ctx, int32_t* rowptr, int32_t* colidx
     return STA_OK;
 }
 
-sta_status sta_last_frame_stats(sta_ctx* ctx, void* stream, int64_t* touched_blocks, int64_t* touched_slots,
-                                int64_t* touched_incidences, int64_t* changed, int64_t* activated)
+sta_status sta_last_frame_stats(sta_ctx* ctx, void* stream, int64_t* out, int n_out)
 {
-    if (!ctx)
+    if (!ctx || (n_out > 0 && !out))
         return STA_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipStreamSynchronize(s);
-    const int64_t n = ctx->last_n_edits;
-    std::vector<int32_t> cl((size_t)n * 10);
+    int32_t n_last = 0;
+    if (e == hipSuccess)
+        e = hipMemcpy(&n_last, &ctx->v.ctl->last_n, sizeof(int32_t), hipMemcpyDeviceToHost);
+    const int64_t n = (n_last >= 0 && n_last <= ctx->n_tets) ? n_last : 0;
+    std::vector<BlockDesc> rc((size_t)n * 10);
     std::vector<uint8_t> un((size_t)n);
     int32_t ferr = 0;
     if (e == hipSuccess && n > 0)
-        e = hipMemcpy(cl.data(), ctx->v.claims, sizeof(int32_t) * cl.size(), hipMemcpyDeviceToHost);
+        e = hipMemcpy(rc.data(), ctx->v.rec, sizeof(BlockDesc) * rc.size(), hipMemcpyDeviceToHost);
     if (e == hipSuccess && n > 0)
         e = hipMemcpy(un.data(), ctx->v.undo, un.size(), hipMemcpyDeviceToHost);
     if (e == hipSuccess)
         e = hipMemcpy(&ferr, &ctx->v.ctl->frame_err, sizeof(int32_t), hipMemcpyDeviceToHost);
     if (e != hipSuccess)
         return hip_fail(ctx, e, "stats copy");
-    int64_t nb = 0, ns = 0, ni = 0, nc = 0, na = 0;
+    int64_t st[STA_NUM_FRAME_STATS] = {0};
+    st[7] = n;
+    st[8] = (n > 0 && ferr != 0) ? 1 : 0;
     if (n > 0 && ferr == 0) {
         for (int64_t i = 0; i < n; ++i) {
             for (int j = 0; j < 10; ++j) {
-                const int32_t b = cl[10 * i + j];
-                if (b < 0)
-                    continue;
-                ++nb;
-                if (j < 4) {
-                    ns += 9;
-                    ni += ctx->h_dseg[b + 1] - ctx->h_dseg[b];
-                } else {
-                    ns += 18;
-                    ni += ctx->h_oseg[b + 1] - ctx->h_oseg[b];
+                const BlockDesc& d = rc[10 * i + j];
+                if (d.kind == 0) {
+                    st[0] += 1;
+                    st[2] += d.k1 - d.k0;
+                    st[4] += 9;
+                } else if (d.kind == 1) {
+                    st[1] += 1;
+                    st[3] += d.k1 - d.k0;
+                    st[4] += 18;
                 }
             }
             if (un[i] != 0xFF) {
-                ++nc;
+                st[5] += 1;
                 if (un[i] == 0)
-                    ++na;
+                    st[6] += 1;
             }
         }
     }
-    if (touched_blocks) *touched_blocks = nb;
-    if (touched_slots) *touched_slots = ns;
-    if (touched_incidences) *touched_incidences = ni;
-    if (changed) *changed = nc;
-    if (activated) *activated = na;
+    for (int k = 0; k < n_out && k < STA_NUM_FRAME_STATS; ++k)
+        out[k] = st[k];
+    return STA_OK;
+}
+
+sta_status sta_enable_kernel_timing(sta_ctx* ctx, int on)
+{
+    if (!ctx)
+        return STA_EINVAL;
+    ctx->timing = on != 0;
+    return STA_OK;
+}
+
+sta_status sta_kernel_times(sta_ctx* ctx, void* stream, int64_t* launches, double* ms)
+{
+    if (!ctx || !launches || !ms)
+        return STA_EINVAL;
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e == hipSuccess)
+        e = hipDeviceSynchronize();
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "kernel_times sync");
+    for (int k = 0; k < STA_NUM_KERNELS; ++k) {
+        launches[k] = 0;
+        ms[k] = 0.0;
+    }
+    for (auto& t : ctx->timed) {
+        float dt = 0.0f;
+        if (hipEventElapsedTime(&dt, t.a, t.b) == hipSuccess && t.kernel >= 0 && t.kernel < STA_NUM_KERNELS) {
+            launches[t.kernel] += 1;
+            ms[t.kernel] += dt;
+        }
+        ctx->event_pool.push_back(t.a);
+        ctx->event_pool.push_back(t.b);
+    }
+    ctx->timed.clear();
     return STA_OK;
 }
 
@@ -417,7 +489,6 @@ sta_status sta_set_params(sta_ctx* ctx, const double* x_dev, const double* E_dev
                                      const_cast<double*>(ctx->v.E), static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return hip_fail(ctx, e, "set_params launch");
-    ctx->ver += 1;
     ctx->stale = true;
     return STA_OK;
 }
@@ -459,6 +530,12 @@ void sta_destroy(sta_ctx* ctx)
     if (!ctx)
         return;
     (void)hipDeviceSynchronize();
+    for (auto& t : ctx->timed) {
+        ctx->event_pool.push_back(t.a);
+        ctx->event_pool.push_back(t.b);
+    }
+    for (hipEvent_t ev : ctx->event_pool)
+        (void)hipEventDestroy(ev);
     free_all(ctx);
     delete ctx;
 }

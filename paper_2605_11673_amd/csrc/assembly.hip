@@ -4,16 +4,19 @@
 // Data flow.  Each candidate tet's element matrix is split into its 10 node
 // blocks (4 diagonal, 6 off-diagonal) and stored at the tet's position in
 // each block's incidence segment: the persistent per-element contributions
-// the paper's streaming policy keeps across frames (Sec. 3.5).  A matrix
-// entry is then the sum of its segment's terms whose tet is active, taken in
-// ascending tet id from +0.0.  The full rebuild re-sums every block; the
-// streaming update re-sums only blocks covered by tets whose state changed.
-// Both call the same reduction routine, so they agree bit for bit.
+// the paper's streaming policy keeps across frames (Sec. 3.5).  An inactive
+// tet's slots hold +0.0.  A matrix entry is the sum of its segment's terms,
+// taken in ascending tet id from +0.0.  The full rebuild recomputes every
+// tet's slots (zero for inactive ones) and re-sums every block; the
+// streaming update rewrites the slots of tets whose state changed and
+// re-sums only the blocks they cover.  Both use the same summation routine,
+// so they agree bit for bit with each other and with a rebuild that skips
+// inactive tets (an accumulator that starts at +0.0 never becomes -0.0, so
+// adding +0.0 changes nothing).
 //
 // Floating point: contraction is off for this file and the element formula
 // is evaluated in a fixed order (see include/stafem.h); only IEEE + - * / and
-// |.| are used.  Skipping an inactive term equals adding +0.0 because an
-// accumulator that starts at +0.0 can never become -0.0.
+// |.| are used.
 #include <hip/hip_runtime.h>
 
 #include "sta_internal.h"
@@ -26,10 +29,12 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kXcds = 8;
+constexpr int kLanesPerEdit = 78;  // phase 2: 4 diagonal blocks x 6 values + 6 off-diagonal blocks x 9 values
+constexpr int kEditLanes = 16;     // phase 1: one lane per block slot (10 used), power of two
 
 // Workgroups are dispatched round-robin over the 8 XCDs.  Remap so that each
 // XCD walks one contiguous range of the work: neighbouring blocks share
-// segment, mask and CSR cache lines, and each XCD has its own L2.
+// contribution, descriptor and CSR cache lines, and each XCD has its own L2.
 __device__ __forceinline__ int xcd_remap(int wg, int G)
 {
     const int q = G / kXcds, r = G % kXcds;
@@ -109,16 +114,19 @@ __device__ __forceinline__ double entry(const double* ga, const double* gb, doub
     return v;
 }
 
-__constant__ int kDiagP[6] = {0, 0, 0, 1, 1, 2};
-__constant__ int kDiagQ[6] = {0, 1, 2, 1, 2, 2};
+constexpr int PA[6] = {0, 0, 0, 1, 1, 2};
+constexpr int PB[6] = {1, 2, 3, 2, 3, 3};
 
 // Compute tet e's element matrix and store its 78 distinct values at the
-// tet's positions in its 10 block segments.  Off-diagonal blocks are stored
-// in block orientation (row node = smaller node id).
-__device__ __forceinline__ void store_element(const DevView& v, int e, int4 t, const Geo& G)
+// tet's 10 incidence positions.  Off-diagonal blocks are stored in block
+// orientation (row node = smaller node id).  pos: the tet's 10 positions.
+__device__ __forceinline__ void store_element(const DevView& v, int e, int4 t, const int* pos)
 {
+    Geo G;
+    element_geometry(v, e, t, G);
+    if (G.det == 0.0)
+        atomicOr(&v.ctl->err, ERR_DEGENERATE);
     const int id[4] = {t.x, t.y, t.z, t.w};
-    const int* pos = v.e2p + 10 * (size_t)e;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
         const double s = dot3(G.g[a], G.g[a]);
@@ -127,8 +135,6 @@ __device__ __forceinline__ void store_element(const DevView& v, int e, int4 t, c
         dst[1] = make_double2(entry(G.g[a], G.g[a], s, G, 0, 2, true), entry(G.g[a], G.g[a], s, G, 1, 1, true));
         dst[2] = make_double2(entry(G.g[a], G.g[a], s, G, 1, 2, true), entry(G.g[a], G.g[a], s, G, 2, 2, true));
     }
-    constexpr int PA[6] = {0, 0, 0, 1, 1, 2};
-    constexpr int PB[6] = {1, 2, 3, 2, 3, 3};
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         const bool sw = id[PA[q]] > id[PB[q]];
@@ -148,183 +154,359 @@ __device__ __forceinline__ void store_element(const DevView& v, int e, int4 t, c
     }
 }
 
-// The canonical sum of one value of one block: +0.0 plus the active terms in
-// segment (ascending tet id) order.
-__device__ __forceinline__ double reduce_terms(const int32_t* __restrict__ inc, const double* __restrict__ c,
-                                               int stride, int v, int k0, int k1,
-                                               const uint8_t* __restrict__ mask)
+// Zero the 78 slots of an inactive tet.
+__device__ __forceinline__ void zero_element(const DevView& v, const int* pos)
+{
+    const double2 z = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        double2* dst = reinterpret_cast<double2*>(v.cd + 6 * (size_t)pos[a]);
+        dst[0] = z;
+        dst[1] = z;
+        dst[2] = z;
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        double* dst = v.co + 9 * (size_t)pos[4 + q];
+#pragma unroll
+        for (int j = 0; j < 9; ++j)
+            dst[j] = 0.0;
+    }
+}
+
+// The canonical sum of value vi of one block: +0.0 plus the segment's terms
+// in ascending tet id.  Loads are issued CH at a time so that a whole
+// segment (up to CH terms) is in flight at once; padding terms are +0.0.
+template <int CH>
+__device__ __forceinline__ double seg_sum(const double* __restrict__ c, int stride, int vi, int k0, int k1)
 {
     double acc = 0.0;
-    for (int k = k0; k < k1; ++k) {
-        const int e = inc[k];
-        const double t = c[(size_t)k * stride + v];
-        if (mask[e])
-            acc = acc + t;
+    for (int base = k0; base < k1; base += CH) {
+        double t[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j)
+            t[j] = (base + j < k1) ? c[(size_t)(base + j) * stride + vi] : 0.0;
+#pragma unroll
+        for (int j = 0; j < CH; ++j)
+            acc = acc + t[j];
     }
     return acc;
 }
 
-__device__ __forceinline__ void reduce_diag_value(const DevView& v, int b, int vi)
+__device__ __constant__ int kDiagP[6] = {0, 0, 0, 1, 1, 2};
+__device__ __constant__ int kDiagQ[6] = {0, 1, 2, 1, 2, 2};
+
+// Recompute value vi (0..5 unique diagonal values, 0..8 off-diagonal) of the
+// block described by d and write it (and its mirror) into the CSR values.
+__device__ __forceinline__ void block_value(const DevView& v, const BlockDesc& d, int vi)
 {
-    const int k0 = v.dseg[b], k1 = v.dseg[b + 1];
-    const int2 meta = v.dmeta[b];
-    const double acc = reduce_terms(v.dinc, v.cd, 6, vi, k0, k1, v.mask);
-    const int p = kDiagP[vi], q = kDiagQ[vi];
-    v.values[meta.x + p * meta.y + q] = acc;
-    if (p != q)
-        v.values[meta.x + q * meta.y + p] = acc;
+    if (d.kind == 0) {
+        const double acc = seg_sum<32>(v.cd, 6, vi, d.k0, d.k1);
+        const int p = kDiagP[vi], q = kDiagQ[vi];
+        v.values[d.up + p * d.rl + q] = acc;
+        if (p != q)
+            v.values[d.up + q * d.rl + p] = acc;
+    } else {
+        const double acc = seg_sum<8>(v.co, 9, vi, d.k0, d.k1);
+        const int p = vi / 3, q = vi - 3 * (vi / 3);
+        v.values[d.up + p * d.rl + q] = acc;
+        v.values[d.lo + q * d.rlj + p] = acc;
+    }
 }
 
-__device__ __forceinline__ void reduce_off_value(const DevView& v, int b, int vi)
+__device__ __forceinline__ BlockDesc load_desc(const BlockDesc* p)
 {
-    const int k0 = v.oseg[b], k1 = v.oseg[b + 1];
-    const int4 meta = v.ometa[b];
-    const double acc = reduce_terms(v.oinc, v.co, 9, vi, k0, k1, v.mask);
-    const int p = vi / 3, q = vi - 3 * (vi / 3);
-    v.values[meta.x + p * meta.y + q] = acc;
-    v.values[meta.z + q * meta.w + p] = acc;
+    const int4* q = reinterpret_cast<const int4*>(p);
+    const int4 a = q[0], b = q[1];
+    BlockDesc d;
+    d.k0 = a.x;
+    d.k1 = a.y;
+    d.up = a.z;
+    d.rl = a.w;
+    d.lo = b.x;
+    d.rlj = b.y;
+    d.kind = b.z;
+    d.block = b.w;
+    return d;
+}
+
+__device__ __forceinline__ void store_desc(BlockDesc* p, const BlockDesc& d)
+{
+    int4* q = reinterpret_cast<int4*>(p);
+    q[0] = make_int4(d.k0, d.k1, d.up, d.rl);
+    q[1] = make_int4(d.lo, d.rlj, d.kind, d.block);
 }
 
 // ---------------------------------------------------------------------------
 // Full rebuild
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_element(DevView v, int all_tets, uint32_t ver)
+// Every candidate: active -> element matrix into its slots, inactive -> zeros.
+__global__ __launch_bounds__(kBlock) void k_element(DevView v)
 {
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
     const int e = wg * kBlock + threadIdx.x;
     if (e >= v.n_tets)
         return;
-    if (!all_tets && !v.mask[e])
-        return;
-    const int4 t = v.T[e];
-    Geo G;
-    element_geometry(v, e, t, G);
-    if (G.det == 0.0)
-        atomicOr(&v.ctl->err, ERR_DEGENERATE);
-    store_element(v, e, t, G);
-    v.cver[e] = ver;
+    int pos[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j)
+        pos[j] = v.e2p[10 * (size_t)e + j];
+    if (v.mask[e])
+        store_element(v, e, v.T[e], pos);
+    else
+        zero_element(v, pos);
 }
 
+// Lanes: 6 per diagonal block, then 9 per off-diagonal block.
 __global__ __launch_bounds__(kBlock) void k_reduce_all(DevView v)
 {
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t t = (int64_t)wg * kBlock + threadIdx.x;
     const int64_t nd6 = (int64_t)v.nd * 6;
+    int b, vi;
     if (t < nd6) {
-        reduce_diag_value(v, (int)(t / 6), (int)(t % 6));
+        b = (int)(t / 6);
+        vi = (int)(t - 6 * (int64_t)b);
     } else {
         const int64_t u = t - nd6;
-        if (u < (int64_t)v.no * 9)
-            reduce_off_value(v, (int)(u / 9), (int)(u % 9));
+        if (u >= (int64_t)v.no * 9)
+            return;
+        const int o = (int)(u / 9);
+        vi = (int)(u - 9 * (int64_t)o);
+        b = v.nd + o;
     }
+    block_value(v, load_desc(v.desc + b), vi);
 }
 
 // ---------------------------------------------------------------------------
 // Streaming update
 // ---------------------------------------------------------------------------
 
-// Phase 1, one thread per edit: validate, de-duplicate the tet, flip its mask
-// bit, refresh its contributions if they predate the current parameters,
-// and claim each of its 10 blocks for this frame (the first claimant of a
-// block records it; later ones see the frame's stamp).  The last workgroup
-// to finish publishes the frame's error bits and advances the epoch.
-__global__ __launch_bounds__(kBlock) void k_edits(DevView v, const int32_t* __restrict__ ids,
-                                                  const uint8_t* __restrict__ states, int32_t n_host,
-                                                  const int32_t* __restrict__ n_dev, uint32_t ver)
+// Write the values of local block (A, B) of tet e (block orientation: row
+// vertex = the one with the smaller node id; same arithmetic as store_element).
+template <int A, int B>
+__device__ __forceinline__ void store_slot_ab(const DevView& v, const Geo& G, const int* id, int pos)
 {
-    const uint32_t epoch = v.ctl->epoch + 1u;
-    const int n = n_dev ? *n_dev : n_host;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) {
-        int32_t* cl = v.claims + 10 * (size_t)i;
-        int32_t mine[10];
+    if (A == B) {
+        const double s = dot3(G.g[A], G.g[A]);
+        double2* dst = reinterpret_cast<double2*>(v.cd + 6 * (size_t)pos);
+        dst[0] = make_double2(entry(G.g[A], G.g[A], s, G, 0, 0, true), entry(G.g[A], G.g[A], s, G, 0, 1, true));
+        dst[1] = make_double2(entry(G.g[A], G.g[A], s, G, 0, 2, true), entry(G.g[A], G.g[A], s, G, 1, 1, true));
+        dst[2] = make_double2(entry(G.g[A], G.g[A], s, G, 1, 2, true), entry(G.g[A], G.g[A], s, G, 2, 2, true));
+    } else {
+        const bool sw = id[A] > id[B];
+        double ga[3], gb[3];
 #pragma unroll
-        for (int j = 0; j < 10; ++j)
-            mine[j] = -1;
-        uint8_t undo = 0xFF;
-        const int id = ids[i];
-        const unsigned st = states[i];
-        if (id < 0 || id >= v.n_tets || st > 1u) {
-            atomicOr(&v.ctl->ferr, ERR_RANGE);
-        } else if (atomicExch(&v.estamp[id], epoch) == epoch) {
-            atomicOr(&v.ctl->ferr, ERR_DUP);
-        } else {
-            const uint8_t prev = v.mask[id];
-            if (prev != st) {
-                v.mask[id] = (uint8_t)st;
-                undo = prev;
-                if (st && v.cver[id] != ver) {
-                    const int4 t = v.T[id];
-                    Geo G;
-                    element_geometry(v, id, t, G);
-                    store_element(v, id, t, G);
-                    v.cver[id] = ver;
-                }
-                const int32_t* eb = v.e2b + 10 * (size_t)id;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int b = eb[j];
-                    if (atomicExch(&v.dstamp[b], epoch) != epoch)
-                        mine[j] = b;
-                }
-#pragma unroll
-                for (int j = 4; j < 10; ++j) {
-                    const int b = eb[j];
-                    if (atomicExch(&v.ostamp[b], epoch) != epoch)
-                        mine[j] = b;
-                }
-            }
+        for (int i = 0; i < 3; ++i) {
+            ga[i] = sw ? G.g[B][i] : G.g[A][i];
+            gb[i] = sw ? G.g[A][i] : G.g[B][i];
         }
+        const double s = dot3(ga, gb);
+        double* dst = v.co + 9 * (size_t)pos;
 #pragma unroll
-        for (int j = 0; j < 10; ++j)
-            cl[j] = mine[j];
-        v.undo[i] = undo;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned arrived = atomicAdd(&v.ctl->done, 1u);
-        if (arrived == gridDim.x - 1) {
-            __threadfence();
-            const int fe = atomicOr(&v.ctl->ferr, 0);
-            v.ctl->frame_err = fe;
-            atomicOr(&v.ctl->err, fe);
-            atomicExch(&v.ctl->ferr, 0);
-            atomicExch(&v.ctl->done, 0u);
-            atomicExch(&v.ctl->epoch, epoch);
-            __threadfence();
-        }
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                dst[3 * i + j] = entry(ga, gb, s, G, i, j, false);
     }
 }
 
+// Write block slot r (0..3 diagonal a=r, 4..9 pairs 01 02 03 12 13 23) of tet
+// e: its element-matrix values or, for an inactive tet, zeros.
+__device__ __forceinline__ void store_slot(const DevView& v, int e, int4 t, int r, int pos, bool active)
+{
+    if (!active) {
+        if (r < 4) {
+            double2* dst = reinterpret_cast<double2*>(v.cd + 6 * (size_t)pos);
+            const double2 z = make_double2(0.0, 0.0);
+            dst[0] = z;
+            dst[1] = z;
+            dst[2] = z;
+        } else {
+            double* dst = v.co + 9 * (size_t)pos;
+#pragma unroll
+            for (int j = 0; j < 9; ++j)
+                dst[j] = 0.0;
+        }
+        return;
+    }
+    Geo G;
+    element_geometry(v, e, t, G);
+    if (G.det == 0.0 && r == 0)
+        atomicOr(&v.ctl->err, ERR_DEGENERATE);
+    const int id[4] = {t.x, t.y, t.z, t.w};
+    switch (r) {
+    case 0: store_slot_ab<0, 0>(v, G, id, pos); break;
+    case 1: store_slot_ab<1, 1>(v, G, id, pos); break;
+    case 2: store_slot_ab<2, 2>(v, G, id, pos); break;
+    case 3: store_slot_ab<3, 3>(v, G, id, pos); break;
+    case 4: store_slot_ab<0, 1>(v, G, id, pos); break;
+    case 5: store_slot_ab<0, 2>(v, G, id, pos); break;
+    case 6: store_slot_ab<0, 3>(v, G, id, pos); break;
+    case 7: store_slot_ab<1, 2>(v, G, id, pos); break;
+    case 8: store_slot_ab<1, 3>(v, G, id, pos); break;
+    default: store_slot_ab<2, 3>(v, G, id, pos); break;
+    }
+}
+
+__device__ __forceinline__ BlockDesc empty_desc()
+{
+    return BlockDesc{0, 0, 0, 0, 0, 0, -1, -1};
+}
+
+// Edit count of this frame: *n_dev if given and within [0, n_host], else n_host.
+__device__ __forceinline__ int frame_count(int32_t n_host, const int32_t* n_dev, bool& bad)
+{
+    bad = false;
+    if (!n_dev)
+        return n_host;
+    const int n = *n_dev;
+    if (n < 0 || n > n_host) {
+        bad = true;
+        return 0;
+    }
+    return n;
+}
+
+// Phase 1, 16 lanes per edit (lane r < 10 owns block slot r).  Validate the
+// edit; lane 0 takes the tet's stamp (a second edit of the same tet in this
+// frame finds it taken: duplicate) and reads its mask bit.  If the state
+// changes, each slot lane claims its block (first claimant wins; the claim
+// record carries the block descriptor), the owner flips the mask bit and the
+// slot lanes rewrite the tet's 78 contribution slots (element matrix on
+// activation, zeros on deactivation).  Each workgroup writes its error bits
+// to its own byte, so no global word needs resetting between frames.
+__global__ __launch_bounds__(kBlock) void k_edits(DevView v, const int32_t* __restrict__ ids,
+                                                  const uint8_t* __restrict__ states, int32_t n_host,
+                                                  const int32_t* __restrict__ n_dev)
+{
+    __shared__ int s_bits;
+    if (threadIdx.x == 0)
+        s_bits = 0;
+    __syncthreads();
+    bool bad_n;
+    const int n = frame_count(n_host, n_dev, bad_n);
+    const int gt = blockIdx.x * kBlock + threadIdx.x;
+    const int i = gt / kEditLanes;
+    const int r = gt - i * kEditLanes;
+    int bits = (bad_n && gt == 0) ? ERR_RANGE : 0;
+    if (i < n) {
+        BlockDesc* rec = v.rec + 10 * (size_t)i;
+        const int id = ids[i];
+        const unsigned st = states[i];
+        if (id < 0 || id >= v.n_tets || st > 1u) {
+            if (r == 0) {
+                bits |= ERR_RANGE;
+                v.undo[i] = 0xFF;
+            }
+            if (r < 10)
+                store_desc(rec + r, empty_desc());
+        } else {
+            int eb = 0, ep = 0;
+            if (r < 10) {
+                eb = v.e2b[10 * (size_t)id + r];
+                ep = v.e2p[10 * (size_t)id + r];
+            }
+            const uint8_t prev = v.mask[id];
+            int owner = 1;
+            if (r == 0)
+                owner = atomicExch(&v.estamp[id], 1u) == 0u ? 1 : 0;
+            const int lane = threadIdx.x & 63;
+            owner = __shfl(owner, lane & ~(kEditLanes - 1), 64);
+            const bool change = prev != st;
+            if (r < 10) {
+                BlockDesc d = empty_desc();
+                if (change) {
+                    const BlockDesc bd = load_desc(v.desc + eb);
+                    if (atomicExch(&v.bstamp[eb], 1u) == 0u)
+                        d = bd;
+                }
+                store_desc(rec + r, d);
+            }
+            if (!owner) {
+                if (r == 0)
+                    bits |= ERR_DUP;
+            } else if (change) {
+                if (r == 0)
+                    v.mask[id] = (uint8_t)st;
+                if (r < 10)
+                    store_slot(v, id, v.T[id], r, ep, st != 0u);
+            }
+            if (r == 0)
+                v.undo[i] = (owner && change) ? prev : (uint8_t)0xFF;
+        }
+    }
+    if (bits)
+        atomicOr(&s_bits, bits);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        v.wg_err[blockIdx.x] = (uint8_t)s_bits;
+}
+
 // Phase 2: 78 lanes per edit (4 diagonal blocks x 6 values, 6 off-diagonal
-// blocks x 9 values); a lane recomputes its value if the edit claimed the
-// block.  If the frame had an error, lane 0 of each edit restores the mask
-// instead and nothing else changes.
+// blocks x 9 values).  Every workgroup first ORs the edit workgroups' error
+// bytes.  Without an error a lane re-sums its value if the edit claimed the
+// block; with one, lane 0 of each edit undoes its mask flip and slot rewrite.
+// Either way the frame's stamps are cleared for the next frame.
 __global__ __launch_bounds__(kBlock) void k_touched(DevView v, const int32_t* __restrict__ ids, int32_t n_host,
                                                     const int32_t* __restrict__ n_dev)
 {
-    const int n = n_dev ? *n_dev : n_host;
+    __shared__ int s_bits;
+    if (threadIdx.x == 0)
+        s_bits = 0;
+    __syncthreads();
+    bool bad_n;
+    const int n = frame_count(n_host, n_dev, bad_n);
+    const int g_edits = n > 0 ? (n * kEditLanes + kBlock - 1) / kBlock : 1;
+    int bits = 0;
+    for (int w = threadIdx.x; w < g_edits; w += kBlock)
+        bits |= v.wg_err[w];
+    if (bits)
+        atomicOr(&s_bits, bits);
+    __syncthreads();
+    const int fe = s_bits;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        v.ctl->frame_err = fe;
+        v.ctl->last_n = n;
+        if (fe)
+            atomicOr(&v.ctl->err, fe);
+    }
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int i = (int)(t / 78);
-    const int r = (int)(t - (int64_t)i * 78);
+    const int i = (int)(t / kLanesPerEdit);
+    const int r = (int)(t - (int64_t)i * kLanesPerEdit);
     if (i >= n)
         return;
-    if (v.ctl->frame_err) {
-        if (r == 0 && v.undo[i] != 0xFF)
-            v.mask[ids[i]] = v.undo[i];
-        return;
-    }
+    int j, vi;
     if (r < 24) {
-        const int b = v.claims[10 * (size_t)i + r / 6];
-        if (b >= 0)
-            reduce_diag_value(v, b, r % 6);
+        j = r / 6;
+        vi = r - 6 * j;
     } else {
-        const int rr = r - 24;
-        const int b = v.claims[10 * (size_t)i + 4 + rr / 9];
-        if (b >= 0)
-            reduce_off_value(v, b, rr % 9);
+        j = 4 + (r - 24) / 9;
+        vi = (r - 24) - 9 * (j - 4);
+    }
+    const BlockDesc d = load_desc(v.rec + 10 * (size_t)i + j);
+    if (!fe && d.kind >= 0)
+        block_value(v, d, vi);
+    if (vi == 0 && d.kind >= 0)
+        v.bstamp[d.block] = 0u;
+    if (r == 0) {
+        const int id = ids[i];
+        if (id >= 0 && id < v.n_tets) {
+            v.estamp[id] = 0u;
+            const uint8_t u = v.undo[i];
+            if (fe && u != 0xFF) {
+                int ep[10];
+#pragma unroll
+                for (int q = 0; q < 10; ++q)
+                    ep[q] = v.e2p[10 * (size_t)id + q];
+                v.mask[id] = u;
+                if (u)
+                    store_element(v, id, v.T[id], ep);
+                else
+                    zero_element(v, ep);
+            }
+        }
     }
 }
 
@@ -349,11 +531,11 @@ inline unsigned blocks_for(int64_t threads)
 
 }  // namespace
 
-hipError_t launch_element(const DevView& v, bool all_tets, uint32_t ver, hipStream_t s)
+hipError_t launch_element(const DevView& v, hipStream_t s)
 {
     if (v.n_tets == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_element, dim3(blocks_for(v.n_tets)), dim3(kBlock), 0, s, v, all_tets ? 1 : 0, ver);
+    hipLaunchKernelGGL(k_element, dim3(blocks_for(v.n_tets)), dim3(kBlock), 0, s, v);
     return hipGetLastError();
 }
 
@@ -366,18 +548,19 @@ hipError_t launch_reduce_all(const DevView& v, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_edits(const DevView& v, const int32_t* ids, const uint8_t* states, int32_t n, uint32_t ver,
-                        hipStream_t s)
+hipError_t launch_edit_phase(const DevView& v, const int32_t* ids, const uint8_t* states, int32_t n_host,
+                             const int32_t* n_dev, hipStream_t s)
 {
-    if (n == 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(k_edits, dim3(blocks_for(n)), dim3(kBlock), 0, s, v, ids, states, n,
-                       (const int32_t*)nullptr, ver);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess)
-        return err;
-    hipLaunchKernelGGL(k_touched, dim3(blocks_for((int64_t)n * 78)), dim3(kBlock), 0, s, v, ids, n,
-                       (const int32_t*)nullptr);
+    // an empty list still runs one workgroup of each phase: they record the frame (count 0)
+    hipLaunchKernelGGL(k_edits, dim3(n_host > 0 ? blocks_for((int64_t)n_host * kEditLanes) : 1u), dim3(kBlock), 0, s, v, ids, states, n_host, n_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_touched_phase(const DevView& v, const int32_t* ids, int32_t n_host, const int32_t* n_dev,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_touched, dim3(n_host > 0 ? blocks_for((int64_t)n_host * kLanesPerEdit) : 1u), dim3(kBlock), 0, s, v, ids,
+                       n_host, n_dev);
     return hipGetLastError();
 }
 
@@ -385,6 +568,8 @@ hipError_t launch_set_params(const DevView& v, const double* x_aos, const double
                              double* zs, double* Eout, hipStream_t s)
 {
     const int64_t n = v.n_nodes > v.n_tets ? v.n_nodes : v.n_tets;
+    if (n == 0)
+        return hipSuccess;
     hipLaunchKernelGGL(k_set_params, dim3(blocks_for(n)), dim3(kBlock), 0, s, v.n_nodes, v.n_tets, x_aos, E, xs,
                        ys, zs, Eout);
     return hipGetLastError();

@@ -22,12 +22,10 @@ enum : int32_t {
 // Control words kept in device memory so that a frame never needs the host
 // (and can be replayed from a captured graph).
 struct Ctl {
-    uint32_t epoch;      // frames started; stamps equal to epoch+1 belong to the frame in flight
-    int32_t ferr;        // error bits of the frame in flight (edit kernel)
-    int32_t frame_err;   // error bits of the last finished edit phase (read by the reduce phase)
     int32_t err;         // sticky error bits, cleared by sta_status_sync
-    uint32_t done;       // edit-phase workgroups finished (last one publishes and resets)
-    int32_t pad[3];
+    int32_t frame_err;   // error bits of the last frame (written by the reduce phase)
+    int32_t last_n;      // edit count of the last frame (statistics; also right under graph replay)
+    int32_t pad;
 };
 
 // Material constants, evaluated once on the host in the fixed order.
@@ -38,7 +36,23 @@ struct Material {
     double rho;
 };
 
+// One 3x3 node block of the matrix (diagonal blocks first, then the
+// off-diagonal blocks i < j in ascending (i, j)).  32 bytes so a lane reads it
+// with two 16-byte loads.
+struct BlockDesc {
+    int32_t k0, k1;  // incidence range: into cd (diagonal) or co (off-diagonal)
+    int32_t up, rl;  // CSR index of entry (3i, 3j) and row length 3*deg(i)
+    int32_t lo, rlj; // CSR index of entry (3j, 3i) and row length 3*deg(j) (diagonal: = up, rl)
+    int32_t kind;    // 0 diagonal, 1 off-diagonal, -1 empty claim record
+    int32_t block;   // block id
+};
+
 // Everything the kernels need, passed by value.
+//
+// Invariant kept by every kernel: the contributions of an inactive tet are
+// +0.0 in all 78 of its incidence slots.  Block sums then run over the whole
+// segment without looking at the mask, and adding those +0.0 terms gives the
+// same bits as skipping them.
 struct DevView {
     int32_t n_nodes, n_tets;
     int32_t nd, no;               // diagonal / off-diagonal 3x3 blocks
@@ -48,36 +62,24 @@ struct DevView {
     const int4* T;                // tets
     const double* E;
     uint8_t* mask;
-    // diagonal blocks: segment offsets into dinc, element id per incidence,
-    // (CSR index of entry (3i,3i), row length 3*deg(i))
-    const int32_t* dseg;
-    const int32_t* dinc;
-    const int2* dmeta;
-    // off-diagonal blocks (i<j): (CSR index of (3i,3j), row length of i,
-    // CSR index of (3j,3i), row length of j)
-    const int32_t* oseg;
-    const int32_t* oinc;
-    const int4* ometa;
-    // per element: 4 diagonal then 6 off-diagonal block ids / incidence positions,
-    // local pair order 00 11 22 33 | 01 02 03 12 13 23
+    const BlockDesc* desc;        // nd + no blocks
+    // per tet, local pair order 00 11 22 33 | 01 02 03 12 13 23: block ids and
+    // incidence positions (into cd for the first 4, into co for the other 6)
     const int32_t* e2b;
     const int32_t* e2p;
     double* cd;                   // 6 unique values per diagonal incidence
     double* co;                   // 9 values per off-diagonal incidence (block orientation)
-    uint32_t* cver;               // parameter version each element's contribution was computed at
     double* values;               // CSR values
     // streaming state
-    uint32_t* estamp;             // per tet: epoch of the last edit naming it
-    uint32_t* dstamp;             // per diagonal block: epoch of the last claim
-    uint32_t* ostamp;             // per off-diagonal block
-    int32_t* claims;              // per edit: 10 claimed block ids (or -1)
+    // Stamps are 1 only while a frame is in flight: the edit phase sets them,
+    // the reduce phase clears the ones it set.
+    uint32_t* estamp;             // per tet: taken by an edit of this frame
+    uint32_t* bstamp;             // per block: claimed in this frame
+    BlockDesc* rec;               // per edit: 10 claim records (kind -1 = not claimed)
     uint8_t* undo;                // per edit: previous mask value, 0xFF = nothing to undo
+    uint8_t* wg_err;              // per edit-phase workgroup: its error bits (always written)
     Ctl* ctl;
     Material mat;
-};
-
-struct DevBuffers {
-    std::vector<void*> owned;
 };
 
 }  // namespace sta
@@ -85,26 +87,34 @@ struct DevBuffers {
 struct sta_ctx {
     int64_t n_nodes = 0, n_tets = 0, n_rows = 0, nnz = 0, nd = 0, no = 0;
     double nu = 0, rho = 0, dt = 0;
-    uint32_t ver = 1;     // parameter version
     bool stale = false;
-    int64_t last_n_edits = 0;
     int device = 0;
     sta::DevView v{};
     int32_t* rowptr = nullptr;  // device
     int32_t* colidx = nullptr;  // device
     std::vector<void*> owned;   // every device allocation
-    // host copies for statistics
-    std::vector<int32_t> h_dseg, h_oseg;
     std::string errmsg;
+    // per-kernel event timing
+    bool timing = false;
+    struct TimedLaunch {
+        int kernel;
+        hipEvent_t a, b;
+    };
+    std::vector<TimedLaunch> timed;
+    std::vector<hipEvent_t> event_pool;
 };
 
 namespace sta {
 
 // Kernel launchers (assembly.hip).
-hipError_t launch_element(const DevView& v, bool all_tets, uint32_t ver, hipStream_t s);
+hipError_t launch_element(const DevView& v, hipStream_t s);
 hipError_t launch_reduce_all(const DevView& v, hipStream_t s);
-hipError_t launch_edits(const DevView& v, const int32_t* ids, const uint8_t* states, int32_t n,
-                        uint32_t ver, hipStream_t s);
+// Streaming phases.  n_dev (device int32, may be NULL) overrides n_host, which
+// then only sizes the grid (an upper bound on the edit count).
+hipError_t launch_edit_phase(const DevView& v, const int32_t* ids, const uint8_t* states, int32_t n_host,
+                             const int32_t* n_dev, hipStream_t s);
+hipError_t launch_touched_phase(const DevView& v, const int32_t* ids, int32_t n_host, const int32_t* n_dev,
+                                hipStream_t s);
 hipError_t launch_set_params(const DevView& v, const double* x_aos, const double* E, double* xs, double* ys,
                              double* zs, double* Eout, hipStream_t s);
 

@@ -43,12 +43,15 @@ SIGNATURES = {
     "sta_build_pattern": (_int, [_vp, _i64, _vp, _i64, _vp, _dbl, _dbl, _dbl, _vp, _vp, ctypes.POINTER(_vp)]),
     "sta_full_rebuild": (_int, [_vp, _vp]),
     "sta_apply_edits": (_int, [_vp, _vp, _vp, _i64, _vp]),
+    "sta_apply_edits_dev": (_int, [_vp, _vp, _vp, _vp, _i64, _vp]),
     "sta_values_ptr": (_vp, [_vp]),
     "sta_copy_values": (_int, [_vp, _vp, _vp]),
     "sta_sizes": (_int, [_vp, _i64p, _i64p, _i64p, _i64p]),
     "sta_pattern_ptrs": (_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "sta_pattern_host": (_int, [_vp, _vp, _vp]),
-    "sta_last_frame_stats": (_int, [_vp, _vp, _i64p, _i64p, _i64p, _i64p, _i64p]),
+    "sta_last_frame_stats": (_int, [_vp, _vp, _i64p, _int]),
+    "sta_enable_kernel_timing": (_int, [_vp, _int]),
+    "sta_kernel_times": (_int, [_vp, _vp, _i64p, ctypes.POINTER(_dbl)]),
     "sta_set_params": (_int, [_vp, _vp, _vp, _vp]),
     "sta_status_sync": (_int, [_vp, _vp]),
     "sta_last_error": (ctypes.c_char_p, [_vp]),
@@ -151,6 +154,15 @@ class Assembler:
                                       _dev_ptr(states) if ids.numel() else None, int(ids.numel()),
                                       _stream_handle(stream)), self._ctx)
 
+    def apply_edits_dev(self, ids: torch.Tensor, states: torch.Tensor, n_dev: torch.Tensor, stream=None):
+        """Edit count read on the device from n_dev (int32 CUDA tensor, 1 element);
+        ids/states are buffers of capacity len(ids).  Graph-capturable."""
+        if (ids.dtype != torch.int32 or states.dtype != torch.uint8 or n_dev.dtype != torch.int32
+                or not (ids.is_cuda and states.is_cuda and n_dev.is_cuda) or ids.numel() != states.numel()):
+            raise TypeError("ids int32, states uint8 (same length) and n_dev int32 CUDA tensors")
+        _check(load().sta_apply_edits_dev(self._ctx, _dev_ptr(ids), _dev_ptr(states), _dev_ptr(n_dev),
+                                          int(ids.numel()), _stream_handle(stream)), self._ctx)
+
     def values_ptr(self) -> int:
         return int(load().sta_values_ptr(self._ctx) or 0)
 
@@ -172,12 +184,28 @@ class Assembler:
         _check(load().sta_pattern_ptrs(self._ctx, ctypes.byref(rp), ctypes.byref(ci), ctypes.byref(mk)), self._ctx)
         return rp.value, ci.value, mk.value
 
+    FRAME_STATS = ("diag_blocks", "off_blocks", "diag_incidences", "off_incidences", "touched_slots",
+                   "changed", "activated", "edits", "rolled_back")
+
     def last_frame_stats(self, stream=None) -> dict:
-        v = [_i64() for _ in range(5)]
-        _check(load().sta_last_frame_stats(self._ctx, _stream_handle(stream), *[ctypes.byref(a) for a in v]),
-               self._ctx)
-        keys = ("touched_blocks", "touched_slots", "touched_incidences", "changed", "activated")
-        return {k: a.value for k, a in zip(keys, v)}
+        out = (ctypes.c_int64 * len(self.FRAME_STATS))()
+        _check(load().sta_last_frame_stats(self._ctx, _stream_handle(stream), out, len(out)), self._ctx)
+        d = dict(zip(self.FRAME_STATS, list(out)))
+        d["touched_blocks"] = d["diag_blocks"] + d["off_blocks"]
+        d["touched_incidences"] = d["diag_incidences"] + d["off_incidences"]
+        return d
+
+    KERNELS = ("element", "reduce", "edits", "touched", "adjoint", "solve", "batch", "spare")
+
+    def enable_kernel_timing(self, on: bool = True):
+        _check(load().sta_enable_kernel_timing(self._ctx, 1 if on else 0), self._ctx)
+
+    def kernel_times(self, stream=None) -> dict:
+        """{kernel: (launches, total ms)} since the last call; synchronises."""
+        n = (ctypes.c_int64 * len(self.KERNELS))()
+        ms = (ctypes.c_double * len(self.KERNELS))()
+        _check(load().sta_kernel_times(self._ctx, _stream_handle(stream), n, ms), self._ctx)
+        return {k: (int(n[i]), float(ms[i])) for i, k in enumerate(self.KERNELS) if n[i]}
 
     def set_params(self, x: torch.Tensor | None = None, E: torch.Tensor | None = None, stream=None):
         """x: (n, 3) float64 CUDA tensor, E: (m,) float64 CUDA tensor; either may be None."""

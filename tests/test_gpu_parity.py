@@ -121,6 +121,7 @@ def test_edit_semantics_and_rollback():
     # empty edit list
     asm.apply_edits(*S.upload_frame(np.zeros(0, np.int32), np.zeros(0, np.uint8)))
     assert_bitwise(gpu_values(asm), v0, "empty edit list")
+    assert asm.last_frame_stats()["edits"] == 0
     # no-op edits (tets already active): nothing is recomputed, nothing changes
     asm.apply_edits(*S.upload_frame(np.array([0, 5, 9], np.int32), np.ones(3, np.uint8)))
     assert asm.last_frame_stats()["touched_blocks"] == 0
@@ -214,3 +215,48 @@ def test_empty_mesh_and_run_twice_determinism():
         runs.append(gpu_values(a))
         a.close()
     assert_bitwise(runs[0], runs[1], "run twice")
+
+
+def test_device_count_and_graph_replay():
+    """sta_apply_edits_dev reads the edit count on the device, so one captured HIP graph
+    serves every frame: new edit lists are copied into the same buffers and the graph is
+    replayed.  Eager frames and synchronisations sit between the replays, and every replay
+    is checked against the oracle."""
+    S = stafem()
+    w = W.make_fracture(seed=3, n=8, counts=[40, 80, 20, 60, 5])
+    frames = list(w.frames) + W.merge_stream(w.frames)
+    pat = oracle.pattern(w.n_nodes, w.tets)
+    asm = S.Assembler.from_workload(w)
+    cap = 128
+    ids = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    st = torch.zeros(cap, dtype=torch.uint8, device="cuda")
+    n = torch.zeros(1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        asm.apply_edits_dev(ids, st, n)
+    torch.cuda.synchronize()
+    assert_bitwise(gpu_values(asm), oracle.rebuild_workload(w, w.mask0, pat), "capture must not execute")
+    mask = w.mask0.copy()
+    for t, (fi, fs) in enumerate(frames):
+        k = len(fi)
+        if t % 3 == 2:  # an eager frame between replays
+            asm.apply_edits(*S.upload_frame(fi, fs))
+        else:
+            ids[:k].copy_(torch.from_numpy(fi.astype(np.int32)))
+            st[:k].copy_(torch.from_numpy(fs.astype(np.uint8)))
+            n.fill_(k)
+            g.replay()
+        torch.cuda.synchronize()
+        mask[fi] = fs
+        assert_bitwise(gpu_values(asm), oracle.rebuild_workload(w, mask, pat), f"graph frame {t}")
+        s = asm.last_frame_stats()
+        assert s["edits"] == k and s["changed"] == k and s["rolled_back"] == 0
+    assert asm.status_sync() == S.STA_OK
+    # a device count above the capacity is an error and the frame is skipped
+    v0 = gpu_values(asm)
+    n.fill_(cap + 1)
+    g.replay()
+    assert asm.status_sync() == S.STA_ERANGE
+    assert_bitwise(gpu_values(asm), v0, "out-of-range device count")
+    asm.close()
