@@ -171,6 +171,31 @@ sta_status sta_kernel_times(sta_ctx* ctx, void* stream, int64_t* launches, doubl
  * sta_full_rebuild.  Asynchronous on `stream`. */
 sta_status sta_set_params(sta_ctx* ctx, const double* x_dev, const double* E_dev, void* stream);
 
+/* Adjoint of the assembly (the differentiable-assembly extension; the paper
+ * itself maintains A_t only): given gA_dev = dL/dvalues (device, nnz), write
+ * g_logE_dev[e] = dL/dlog(E_e) (device, n_tets; 0 for inactive tets) and
+ * g_x_dev[3i+k] = dL/dx_{i,k} (device, n_nodes*3) for the current mask and
+ * parameters, by reverse differentiation of the element formula above.
+ * Per-node sums run over the node's tets in ascending id (reproducible).
+ * Asynchronous on `stream`.  STA_ESTALE after sta_set_params until a rebuild. */
+sta_status sta_adjoint(sta_ctx* ctx, const double* gA_dev, double* g_logE_dev, double* g_x_dev, void* stream);
+
+/* out_dev[s] = alpha * a_dev[row(s)] * b_dev[col(s)] for every pattern slot s
+ * (e.g. the cotangent -lambda u^T of the values behind a linear solve).
+ * a_dev, b_dev: device, n_rows; out_dev: device, nnz.  Asynchronous. */
+sta_status sta_slot_outer(sta_ctx* ctx, const double* a_dev, const double* b_dev, double alpha, double* out_dev,
+                          void* stream);
+
+/* Jacobi-preconditioned CG (Sec. 4; Alg. 1 solve step) on A x = b with the
+ * matrix values_dev (device, nnz, this context's pattern; NULL = the
+ * context's own values).  Rows with a zero diagonal (nodes with no active
+ * tet) are held at x = 0 and their b is ignored.  Stops when
+ * ||r|| <= rtol ||b|| or after max_iter iterations.  b_dev, x_dev: device,
+ * n_rows.  Synchronises `stream` (convergence is checked every 16
+ * iterations).  *iters_out / *relres_out (may be NULL) report the result. */
+sta_status sta_cg_solve(sta_ctx* ctx, const double* values_dev, const double* b_dev, double* x_dev, double rtol,
+                        int max_iter, void* stream, int* iters_out, double* relres_out);
+
 /* Synchronise `stream`, return and clear the first error the device
  * recorded (STA_ERANGE, STA_EDUP, STA_EDEGENERATE), else STA_OK. */
 sta_status sta_status_sync(sta_ctx* ctx, void* stream);

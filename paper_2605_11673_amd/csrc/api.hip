@@ -178,7 +178,7 @@ sta_status sta_build_pattern(const double* x, int64_t n_nodes, const int32_t* te
     double *xs, *E_d, *cd, *co, *values;
     int4* T;
     uint8_t *mask, *undo, *wg_err;
-    int32_t *e2b, *e2p;
+    int32_t *e2b, *e2p, *ndiag;
     BlockDesc *desc, *rec;
     uint32_t *estamp, *bstamp;
     Ctl* ctl;
@@ -194,6 +194,7 @@ sta_status sta_build_pattern(const double* x, int64_t n_nodes, const int32_t* te
     ALLOC(c->colidx, P.nnz);
     ALLOC(values, P.nnz);
     ALLOC(desc, nb);
+    ALLOC(ndiag, n_nodes);
     ALLOC(e2b, 10 * n_tets);
     ALLOC(e2p, 10 * n_tets);
     ALLOC(cd, 24 * n_tets);
@@ -239,6 +240,7 @@ sta_status sta_build_pattern(const double* x, int64_t n_nodes, const int32_t* te
     if (e == hipSuccess) e = upload(c->rowptr, P.rowptr.data(), P.rowptr.size(), s);
     if (e == hipSuccess) e = upload(c->colidx, P.colidx.data(), P.colidx.size(), s);
     if (e == hipSuccess) e = upload(desc, hd.data(), hd.size(), s);
+    if (e == hipSuccess) e = upload(ndiag, P.ndiag.data(), P.ndiag.size(), s);
     if (e == hipSuccess) e = upload(e2b, he2b.data(), he2b.size(), s);
     if (e == hipSuccess) e = upload(e2p, P.e2p.data(), P.e2p.size(), s);
     if (e == hipSuccess && n_tets > 0) e = hipMemsetAsync(estamp, 0, sizeof(uint32_t) * n_tets, s);
@@ -253,6 +255,7 @@ sta_status sta_build_pattern(const double* x, int64_t n_nodes, const int32_t* te
     v.E = E_d;
     v.mask = mask;
     v.desc = desc;
+    v.ndiag = ndiag;
     v.e2b = e2b;
     v.e2p = e2p;
     v.cd = cd;
@@ -518,6 +521,107 @@ sta_status sta_status_sync(sta_ctx* ctx, void* stream)
     return st;
 }
 
+sta_status sta_adjoint(sta_ctx* ctx, const double* gA_dev, double* g_logE_dev, double* g_x_dev, void* stream)
+{
+    if (!ctx || (ctx->nnz > 0 && !gA_dev) || (ctx->n_tets > 0 && !g_logE_dev) || (ctx->n_nodes > 0 && !g_x_dev))
+        return STA_EINVAL;
+    if (ctx->stale)
+        return fail(ctx, STA_ESTALE, "parameters changed: call sta_full_rebuild before sta_adjoint");
+    hipError_t e = hipSuccess;
+    if (!ctx->adj_xbar)
+        e = dalloc(ctx, &ctx->adj_xbar, (size_t)12 * ctx->n_tets);
+    if (e != hipSuccess)
+        return fail(ctx, STA_ENOMEM, "adjoint workspace allocation failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    e = timed(ctx, STA_KERNEL_ADJOINT, s,
+              [&] { return launch_adjoint(ctx->v, gA_dev, g_logE_dev, g_x_dev, ctx->adj_xbar, s); });
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "adjoint launch");
+    return STA_OK;
+}
+
+sta_status sta_slot_outer(sta_ctx* ctx, const double* a_dev, const double* b_dev, double alpha, double* out_dev,
+                          void* stream)
+{
+    if (!ctx || (ctx->n_rows > 0 && (!a_dev || !b_dev)) || (ctx->nnz > 0 && !out_dev))
+        return STA_EINVAL;
+    hipError_t e = launch_slot_outer((int)ctx->n_rows, ctx->rowptr, ctx->colidx, a_dev, b_dev, alpha, out_dev,
+                                     static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "slot_outer launch");
+    return STA_OK;
+}
+
+sta_status sta_cg_solve(sta_ctx* ctx, const double* values_dev, const double* b_dev, double* x_dev, double rtol,
+                        int max_iter, void* stream, int* iters_out, double* relres_out)
+{
+    if (!ctx || (ctx->n_rows > 0 && (!b_dev || !x_dev)) || !(rtol >= 0.0) || max_iter < 0)
+        return STA_EINVAL;
+    if (ctx->n_rows == 0) {
+        if (iters_out) *iters_out = 0;
+        if (relres_out) *relres_out = 0.0;
+        return STA_OK;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int n = (int)ctx->n_rows;
+    const int nparts = cg_partials(n);
+    hipError_t e = hipSuccess;
+    if (!ctx->cg_ws) {
+        e = dalloc(ctx, &ctx->cg_ws, (size_t)6 * n + nparts);
+        if (e == hipSuccess)
+            e = dalloc(ctx, &ctx->cg_dpos, (size_t)n);
+        if (e == hipSuccess)
+            e = dalloc(ctx, &ctx->cg_s, 1);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void**)&ctx->cg_host, sizeof(CgScalars), hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = launch_diag_positions(ctx->v, ctx->cg_dpos, s);
+        if (e != hipSuccess) {
+            ctx->cg_ws = nullptr;
+            return fail(ctx, STA_ENOMEM, "CG workspace allocation failed");
+        }
+    }
+    CgView c;
+    c.n = n;
+    c.nparts = (n + 255) / 256;
+    c.rowptr = ctx->rowptr;
+    c.colidx = ctx->colidx;
+    c.vals = values_dev ? values_dev : ctx->v.values;
+    c.dpos = ctx->cg_dpos;
+    c.x = ctx->cg_ws;
+    c.r = c.x + n;
+    c.z = c.r + n;
+    c.p = c.z + n;
+    c.q = c.p + n;
+    c.dinv = c.q + n;
+    c.part = c.dinv + n;
+    c.s = ctx->cg_s;
+    e = launch_cg_init(c, b_dev, rtol, s);
+    const int chunk = 16;
+    int done_iters = 0;
+    while (e == hipSuccess) {
+        const int count = max_iter - done_iters < chunk ? max_iter - done_iters : chunk;
+        if (count > 0)
+            e = timed(ctx, STA_KERNEL_SOLVE, s, [&] { return launch_cg_iterations(c, count, max_iter, s); });
+        done_iters += count;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ctx->cg_host, ctx->cg_s, sizeof(CgScalars), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess || ctx->cg_host->done || done_iters >= max_iter)
+            break;
+    }
+    if (e == hipSuccess)
+        e = launch_cg_output(c, x_dev, s);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "cg");
+    if (iters_out)
+        *iters_out = ctx->cg_host->iters;
+    if (relres_out)
+        *relres_out = ctx->cg_host->bnorm2 > 0.0 ? std::sqrt(ctx->cg_host->rr / ctx->cg_host->bnorm2) : 0.0;
+    return STA_OK;
+}
+
 const char* sta_last_error(const sta_ctx* ctx)
 {
     if (!ctx)
@@ -536,6 +640,8 @@ void sta_destroy(sta_ctx* ctx)
     }
     for (hipEvent_t ev : ctx->event_pool)
         (void)hipEventDestroy(ev);
+    if (ctx->cg_host)
+        (void)hipHostFree(ctx->cg_host);
     free_all(ctx);
     delete ctx;
 }

@@ -160,6 +160,7 @@ std::string build_host_pattern(int64_t n, const int32_t* tets, int64_t m, HostPa
         P.ometa[4 * b + 2] = (int32_t)(P.rowptr[3 * j] + 3 * pos(j, i));
         P.ometa[4 * b + 3] = (int32_t)(3 * (aoff[j + 1] - aoff[j]));
     }
+    P.ndiag.assign(did.begin(), did.end());
     P.nd = nd;
     P.no = no;
     return "";

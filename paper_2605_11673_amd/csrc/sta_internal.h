@@ -63,6 +63,7 @@ struct DevView {
     const double* E;
     uint8_t* mask;
     const BlockDesc* desc;        // nd + no blocks
+    const int32_t* ndiag;         // per node: its diagonal block id, -1 if in no candidate tet
     // per tet, local pair order 00 11 22 33 | 01 02 03 12 13 23: block ids and
     // incidence positions (into cd for the first 4, into co for the other 6)
     const int32_t* e2b;
@@ -82,6 +83,23 @@ struct DevView {
     Material mat;
 };
 
+// Conjugate-gradient workspace (cg.hip).
+struct CgScalars {
+    double rz, alpha, beta, rr, bnorm2, tol2;
+    int32_t iters, done;
+};
+
+struct CgView {
+    int32_t n;        // rows
+    int32_t nparts;   // partial sums per vector kernel (one per 256 rows)
+    const int32_t* rowptr;
+    const int32_t* colidx;
+    const double* vals;
+    const int32_t* dpos;  // diagonal position per row, -1 if none
+    double *x, *r, *z, *p, *q, *dinv, *part;
+    CgScalars* s;
+};
+
 }  // namespace sta
 
 struct sta_ctx {
@@ -93,6 +111,12 @@ struct sta_ctx {
     int32_t* rowptr = nullptr;  // device
     int32_t* colidx = nullptr;  // device
     std::vector<void*> owned;   // every device allocation
+    // lazily allocated workspaces
+    double* cg_ws = nullptr;        // 6 vectors of n_rows + partials
+    int32_t* cg_dpos = nullptr;
+    sta::CgScalars* cg_s = nullptr;
+    sta::CgScalars* cg_host = nullptr;  // pinned
+    double* adj_xbar = nullptr;     // 3 doubles per diagonal incidence
     std::string errmsg;
     // per-kernel event timing
     bool timing = false;
@@ -118,6 +142,17 @@ hipError_t launch_touched_phase(const DevView& v, const int32_t* ids, int32_t n_
 hipError_t launch_set_params(const DevView& v, const double* x_aos, const double* E, double* xs, double* ys,
                              double* zs, double* Eout, hipStream_t s);
 
+// Adjoint and CG launchers (adjoint.hip, cg.hip).
+hipError_t launch_adjoint(const DevView& v, const double* gA, double* g_logE, double* g_x, double* xbar,
+                          hipStream_t s);
+hipError_t launch_slot_outer(int n_rows, const int32_t* rowptr, const int32_t* colidx, const double* a,
+                             const double* b, double alpha, double* out, hipStream_t s);
+hipError_t launch_diag_positions(const DevView& v, int32_t* dpos, hipStream_t s);
+int cg_partials(int n);
+hipError_t launch_cg_init(const CgView& c, const double* b, double rtol, hipStream_t s);
+hipError_t launch_cg_iterations(const CgView& c, int count, int max_iter, hipStream_t s);
+hipError_t launch_cg_output(const CgView& c, double* x, hipStream_t s);
+
 // Host pattern builder (pattern.cpp).  Fills host arrays; returns "" or an error message.
 struct HostPattern {
     int64_t nd = 0, no = 0, nnz = 0;
@@ -126,6 +161,7 @@ struct HostPattern {
     std::vector<int32_t> dmeta;  // 2 per block
     std::vector<int32_t> ometa;  // 4 per block
     std::vector<int32_t> e2b, e2p;  // 10 per element
+    std::vector<int32_t> ndiag;     // per node: diagonal block id or -1
 };
 std::string build_host_pattern(int64_t n_nodes, const int32_t* tets, int64_t n_tets, HostPattern& P);
 

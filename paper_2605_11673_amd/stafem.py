@@ -53,6 +53,9 @@ SIGNATURES = {
     "sta_enable_kernel_timing": (_int, [_vp, _int]),
     "sta_kernel_times": (_int, [_vp, _vp, _i64p, ctypes.POINTER(_dbl)]),
     "sta_set_params": (_int, [_vp, _vp, _vp, _vp]),
+    "sta_adjoint": (_int, [_vp, _vp, _vp, _vp, _vp]),
+    "sta_slot_outer": (_int, [_vp, _vp, _vp, _dbl, _vp, _vp]),
+    "sta_cg_solve": (_int, [_vp, _vp, _vp, _vp, _dbl, _int, _vp, ctypes.POINTER(_int), ctypes.POINTER(_dbl)]),
     "sta_status_sync": (_int, [_vp, _vp]),
     "sta_last_error": (ctypes.c_char_p, [_vp]),
     "sta_destroy": (None, [_vp]),
@@ -90,6 +93,11 @@ def _check(code: int, ctx=None):
 
 def _dev_ptr(t: torch.Tensor) -> _vp:
     return _vp(t.data_ptr())
+
+
+def _need_f64(t: torch.Tensor, n: int):
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+        raise TypeError(f"expected a contiguous float64 CUDA tensor of {n} elements")
 
 
 class Assembler:
@@ -214,6 +222,38 @@ class Assembler:
                 raise TypeError("set_params takes contiguous float64 CUDA tensors")
         _check(load().sta_set_params(self._ctx, _dev_ptr(x) if x is not None else None,
                                      _dev_ptr(E) if E is not None else None, _stream_handle(stream)), self._ctx)
+
+    def adjoint(self, gA: torch.Tensor, stream=None):
+        """(dL/dlogE (m,), dL/dx (n, 3)) float64 CUDA tensors from slot cotangents gA (nnz,)."""
+        _need_f64(gA, self.nnz)
+        gl = torch.empty(self.n_tets, dtype=torch.float64, device="cuda")
+        gx = torch.empty((self.n_nodes, 3), dtype=torch.float64, device="cuda")
+        _check(load().sta_adjoint(self._ctx, _dev_ptr(gA), _dev_ptr(gl), _dev_ptr(gx), _stream_handle(stream)),
+               self._ctx)
+        return gl, gx
+
+    def slot_outer(self, a: torch.Tensor, b: torch.Tensor, alpha: float, stream=None) -> torch.Tensor:
+        """out[s] = alpha * a[row(s)] * b[col(s)] over the pattern (float64 CUDA, nnz)."""
+        _need_f64(a, self.n_rows)
+        _need_f64(b, self.n_rows)
+        out = torch.empty(self.nnz, dtype=torch.float64, device="cuda")
+        _check(load().sta_slot_outer(self._ctx, _dev_ptr(a), _dev_ptr(b), float(alpha), _dev_ptr(out),
+                                     _stream_handle(stream)), self._ctx)
+        return out
+
+    def cg_solve(self, b: torch.Tensor, values: torch.Tensor | None = None, rtol: float = 1e-12,
+                 max_iter: int = 100000, stream=None):
+        """Jacobi-PCG on A x = b (A = values, default the context's own); returns (x, iters, relres)."""
+        b = b.reshape(-1)
+        _need_f64(b, self.n_rows)
+        if values is not None:
+            _need_f64(values, self.nnz)
+        x = torch.empty(self.n_rows, dtype=torch.float64, device="cuda")
+        it, rr = ctypes.c_int(0), ctypes.c_double(0.0)
+        _check(load().sta_cg_solve(self._ctx, _dev_ptr(values) if values is not None else None, _dev_ptr(b),
+                                   _dev_ptr(x), float(rtol), int(max_iter), _stream_handle(stream),
+                                   ctypes.byref(it), ctypes.byref(rr)), self._ctx)
+        return x, it.value, rr.value
 
     def status_sync(self, stream=None) -> int:
         """Synchronise and return (and clear) the first device-detected error code."""

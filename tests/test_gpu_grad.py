@@ -1,0 +1,194 @@
+"""GPU adjoint and CG against the oracle, finite differences and exact identities.
+
+The objective is compliance L = f^T u with A u = f (A symmetric, so the
+adjoint state is u itself and dL/dvalues = -u u^T on the pattern).  The
+GPU adjoint (hand reverse-mode) is compared with the oracle's complex-step
+route, with exact-difference central finite differences, and with the
+identities G2-G5 that follow from the structure of A = M + dt^2 K:
+  G2 dL/dlogE_e = -dt^2 u_e^T K_e u_e <= 0,   G3 sum_e dL/dlogE_e = u^T M u - L,
+  G4 sum_i dL/dx_i = 0,   G5 sum_i x_i . dL/dx_i = -(dt^2 u^T K u + 3 u^T M u).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2605_11673_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def S():
+    from paper_2605_11673_amd import stafem
+    return stafem
+
+
+def small_case(seed=0):
+    w = W.make_fracture(seed=seed, n=5, counts=[20, 40, 30])
+    mask = w.mask_after(2)
+    f = W.loads_for(w, mask, seed)
+    return w, mask, f
+
+
+def build_at(w, mask):
+    asm = S().Assembler(w.x, w.tets, w.E, w.nu, w.rho, w.dt, mask)
+    return asm
+
+
+def rel_err(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def test_adjoint_matches_oracle_random_cotangent():
+    """Arbitrary (non-symmetric) slot cotangents: GPU reverse mode vs oracle complex step."""
+    w, mask, _ = small_case(1)
+    asm = build_at(w, mask)
+    pat = oracle.pattern(w.n_nodes, w.tets)
+    g = np.random.default_rng(5).standard_normal(asm.nnz)
+    gl, gx = asm.adjoint(torch.from_numpy(g).cuda())
+    ol, ox = oracle.adjoint(w.x, w.tets, w.E, w.nu, w.rho, w.dt, mask, pat[0], pat[1], g)
+    gl, gx = gl.cpu().numpy(), gx.cpu().numpy()
+    assert rel_err(gl, ol) <= 1e-11
+    assert rel_err(gx, ox) <= 1e-11
+    assert np.all(gl[mask == 0] == 0.0)
+    asm.close()
+
+
+def test_cg_matches_direct_solve():
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    w, mask, f = small_case(2)
+    asm = build_at(w, mask)
+    pat = oracle.pattern(w.n_nodes, w.tets)
+    vals = asm.values().cpu().numpy()
+    u, it, rr = asm.cg_solve(torch.from_numpy(f.reshape(-1)).cuda(), rtol=1e-13)
+    u = u.cpu().numpy()
+    A = sp.csr_matrix((vals, pat[1], pat[0]), shape=(asm.n_rows,) * 2)
+    live = A.diagonal() != 0
+    ud = spla.spsolve(A[live][:, live].tocsc(), f.reshape(-1)[live])
+    assert rr <= 1e-13 and it > 0
+    assert rel_err(u[live], ud) <= 1e-10
+    assert np.all(u[~live] == 0.0)
+    # reproducible: a second solve gives the same bits
+    u2, it2, _ = asm.cg_solve(torch.from_numpy(f.reshape(-1)).cuda(), rtol=1e-13)
+    assert it2 == it and np.array_equal(u2.cpu().numpy(), u)
+    asm.close()
+
+
+def compliance_gradient(asm, f_dev, rtol=1e-13):
+    u, it, rr = asm.cg_solve(f_dev, rtol=rtol)
+    gA = asm.slot_outer(u, u, -1.0)
+    gl, gx = asm.adjoint(gA)
+    return u, gl, gx, it
+
+
+def test_compliance_gradient_full_size():
+    """384k-tet fracture state after frame 12: GPU gradient vs the oracle's (own PCG +
+    complex step), identities G2-G5, and exact-difference central FD (h = 1e-6) on 20
+    active tets (logE) and 20 nodes (x, 3 components each).
+
+    FD: L(+h) - L(-h) = -u_+^T (A_+ - A_-) u_- with u_+/- from GPU solves at the
+    perturbed parameters.  For logE, A_+ - A_- = ((E_+ - E_-)/E) dt^2 K_e exactly (A is
+    linear in E); forming it by subtracting two rounded matrices would leave an error
+    of eps/(2h) * |K_e| |u_e|^2, which swamps tets of floating fragments (large rigid
+    u_e, tiny strain energy).  Relative error: per tet |fd - g| / |g|; per node the
+    largest component error over the largest component of that node's gradient."""
+    Sm = S()
+    w, mask, f, tet_s, node_s = W.make_gradient_case(0)
+    print(f"[grad] n={w.n_nodes} m={w.n_tets} active={int(mask.sum())}", flush=True)
+    asm = build_at(w, mask)
+    fd = torch.from_numpy(f.reshape(-1)).cuda()
+    u, gl, gx, it = compliance_gradient(asm, fd)
+    u_h, gl_h, gx_h = u.cpu().numpy(), gl.cpu().numpy(), gx.cpu().numpy()
+    L = float(f.reshape(-1) @ u_h)
+    print(f"[grad] GPU CG {it} iterations, L = {L:.12g}", flush=True)
+
+    # oracle: its own rebuild, PCG and complex-step adjoint
+    pat = oracle.pattern(w.n_nodes, w.tets)
+    ov = oracle.rebuild(w.x, w.tets, w.E, w.nu, w.rho, w.dt, mask, *pat)
+    assert np.array_equal(ov.view(np.uint64), asm.values().cpu().numpy().view(np.uint64))
+    ou, oit, orr = oracle.pcg(pat[0], pat[1], ov, f.reshape(-1), rtol=1e-13)
+    assert rel_err(u_h, ou) <= 1e-9
+    r = np.repeat(np.arange(3 * w.n_nodes), np.diff(pat[0]))
+    ol, ox = oracle.adjoint(w.x, w.tets, w.E, w.nu, w.rho, w.dt, mask, pat[0], pat[1], -(ou[r] * ou[pat[1]]))
+    assert rel_err(gl_h, ol) <= 1e-8
+    assert rel_err(gx_h, ox) <= 1e-8
+    print("[grad] oracle agreement ok", flush=True)
+
+    # identities
+    act = mask.astype(bool)
+    vM = oracle.rebuild(w.x, w.tets, np.zeros(w.n_tets), w.nu, w.rho, w.dt, mask, *pat)
+    vK = oracle.rebuild(w.x, w.tets, w.E, w.nu, 0.0, w.dt, mask, *pat)
+    uMu = float(u_h @ oracle.spmv(pat[0], pat[1], vM, u_h))
+    uKu = float(u_h @ oracle.spmv(pat[0], pat[1], vK, u_h))
+    assert np.all(gl_h[act] <= 1e-12 * np.abs(gl_h).max()) and np.all(gl_h[~act] == 0.0)
+    assert abs(gl_h.sum() - (uMu - L)) <= 1e-9 * abs(L)
+    assert np.abs(gx_h.sum(0)).max() <= 1e-9 * np.abs(gx_h).max() * np.sqrt(w.n_nodes)
+    assert abs((w.x * gx_h).sum() + (uKu + 3 * uMu)) <= 1e-8 * (uKu + 3 * uMu)
+
+    # exact-difference central FD: L(+h) - L(-h) = -u_+^T (A_+ - A_-) u_-
+    h = 1e-6
+    xd = torch.from_numpy(w.x).cuda()
+    Ed = torch.from_numpy(w.E).cuda()
+
+    def solve_with(E=None, x=None):
+        asm.set_params(xd if x is None else x, Ed if E is None else E)
+        asm.full_rebuild()
+        return asm.cg_solve(fd, rtol=1e-13)[0].cpu().numpy()
+
+    def local(ring, xp, xm, Ep, Em, up, um):
+        acc = 0.0
+        for e in ring:
+            t = w.tets[e]
+            if Ep is Em:  # x perturbed: A_+ - A_- by subtraction
+                dA = (oracle.element_matrix(xp[t], w.E[e], w.nu, w.rho, w.dt)
+                      - oracle.element_matrix(xm[t], w.E[e], w.nu, w.rho, w.dt))
+            else:  # logE perturbed: A is linear in E, A_+ - A_- = (E_+ - E_-)/E dt^2 K_e
+                dA = ((Ep[e] - Em[e]) / w.E[e]) * oracle.element_matrix(w.x[t], w.E[e], w.nu, 0.0, w.dt)
+            dof = (3 * t[:, None] + np.arange(3)[None, :]).reshape(-1)
+            acc += up[dof] @ dA @ um[dof]
+        return -acc / (2 * h)
+
+    worst = 0.0
+    for e in tet_s:
+        Ep, Em = w.E.copy(), w.E.copy()
+        Ep[e] = np.exp(np.log(w.E[e]) + h)
+        Em[e] = np.exp(np.log(w.E[e]) - h)
+        up = solve_with(E=torch.from_numpy(Ep).cuda())
+        um = solve_with(E=torch.from_numpy(Em).cuda())
+        fdv = local([e], w.x, w.x, Ep, Em, up, um)
+        worst = max(worst, abs(fdv - gl_h[e]) / abs(gl_h[e]))
+    print(f"[grad] logE FD worst relative error {worst:.3e}", flush=True)
+    assert worst < 1e-6
+    worst = 0.0
+    for i in node_s:
+        ring = [e for e in np.nonzero(np.any(w.tets == i, axis=1))[0] if mask[e]]
+        for k in range(3):
+            xp, xm = w.x.copy(), w.x.copy()
+            xp[i, k] += h
+            xm[i, k] -= h
+            up = solve_with(x=torch.from_numpy(xp).cuda())
+            um = solve_with(x=torch.from_numpy(xm).cuda())
+            fdv = local(ring, xp, xm, w.E, w.E, up, um)
+            worst = max(worst, abs(fdv - gx_h[i, k]) / np.abs(gx_h[i]).max())
+    print(f"[grad] x FD worst relative error {worst:.3e}", flush=True)
+    assert worst < 1e-6
+    asm.close()
+
+
+def test_autograd_compliance_matches_adjoint():
+    """L = f . u through assemble() and solve(): .backward() gives the adjoint-kernel gradient."""
+    from paper_2605_11673_amd.autograd import assemble, solve
+    w, mask, f = small_case(3)
+    asm = build_at(w, mask)
+    logE = torch.from_numpy(np.log(w.E)).cuda().requires_grad_(True)
+    x = torch.from_numpy(w.x).cuda().requires_grad_(True)
+    fd = torch.from_numpy(f.reshape(-1)).cuda()
+    vals = assemble(logE, x, asm)
+    u = solve(vals, fd, asm, 1e-13)
+    L = (fd * u).sum()
+    L.backward()
+    u2, gl, gx, _ = compliance_gradient(asm, fd)
+    assert rel_err(logE.grad.cpu().numpy(), gl.cpu().numpy()) <= 1e-9
+    assert rel_err(x.grad.cpu().numpy(), gx.cpu().numpy()) <= 1e-9
+    asm.close()
