@@ -72,6 +72,8 @@ typedef int sta_status;
 #define STA_ESTALE (-5)       /* parameters changed; call sta_full_rebuild first */
 #define STA_ERANGE (-6)       /* an edit id is outside [0, n_tets) or a state is not 0/1 */
 #define STA_EDUP (-7)         /* an edit list names the same tet twice */
+#define STA_ETIMEOUT (-8)     /* a fused frame could not synchronise its grid (GPU shared with
+                                 other work); the frame is incomplete: call sta_full_rebuild */
 
 /* Build the superset pattern and the initial matrix (Sec. 3.1 inputs:
  * vertices, candidate pool, initial mask; Alg. 1 initialisation).
@@ -160,7 +162,7 @@ sta_status sta_last_frame_stats(sta_ctx* ctx, void* stream, int64_t* out, int n_
 #define STA_KERNEL_TOUCHED 3   /* streaming phase 2: re-sum claimed blocks */
 #define STA_KERNEL_ADJOINT 4
 #define STA_KERNEL_SOLVE 5     /* all kernels of one CG solve */
-#define STA_KERNEL_BATCH 6     /* fused batched frame */
+#define STA_KERNEL_FRAME 6     /* fused frame: both streaming phases in one launch */
 #define STA_NUM_KERNELS 8
 sta_status sta_enable_kernel_timing(sta_ctx* ctx, int on);
 sta_status sta_kernel_times(sta_ctx* ctx, void* stream, int64_t* launches, double* ms);
@@ -195,6 +197,49 @@ sta_status sta_slot_outer(sta_ctx* ctx, const double* a_dev, const double* b_dev
  * iterations).  *iters_out / *relres_out (may be NULL) report the result. */
 sta_status sta_cg_solve(sta_ctx* ctx, const double* values_dev, const double* b_dev, double* x_dev, double rtol,
                         int max_iter, void* stream, int* iters_out, double* relres_out);
+
+/* Execution configuration.
+ *   fused       0: a frame is two launches (edit phase, touched phase);
+ *               1: one persistent launch (both phases, grid barrier between).
+ *   rebuild_qd / rebuild_qo, stream_qd / stream_qo: slot mapping, i.e. lanes
+ *               cooperating on one block value for diagonal / off-diagonal
+ *               blocks in the rebuild and in the streaming update
+ *               (diagonal: 1 = thread-, 4 = quad-, 16 = wave-sixteenth-per-slot;
+ *               off-diagonal: 1 or 4).  Every mapping adds the same terms in
+ *               the same order: results are bit-identical.
+ *   grid_cap    upper bound on the fused kernel's workgroups (0 = the
+ *               co-resident limit).
+ * sta_get_config writes the same 6 integers.  Defaults: 0, 1, 1, 1, 1, 0. */
+sta_status sta_set_config(sta_ctx* ctx, int fused, int rebuild_qd, int rebuild_qo, int stream_qd, int stream_qo,
+                          int grid_cap);
+sta_status sta_get_config(const sta_ctx* ctx, int* out6);
+
+/* Autotuner: times every slot mapping for the full rebuild, and every
+ * mapping x {two launches, fused with grid caps} for one streaming frame
+ * (ids_dev / states_dev, device, n_edits; each timed application is undone
+ * before the next), keeps the fastest of each, and returns a text report in
+ * report (may be NULL).  If the environment variable STA_TUNE_CACHE names a
+ * file, a previous result for the same mesh sizes and frame size is reused
+ * from it and new results are appended.  Synchronises `stream`. */
+sta_status sta_autotune(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* states_dev, int64_t n_edits,
+                        int reps, void* stream, char* report, int64_t report_len);
+
+/* Batched build: k independent meshes become one context whose node, tet,
+ * row and value ranges are the meshes' own, concatenated in order (mesh j's
+ * tet t is global tet tet_off[j] + t).  Arguments as for sta_build_pattern,
+ * per mesh (arrays of k host pointers and sizes); nu, rho, dt shared.  A
+ * frame over all meshes is one sta_apply_edits / sta_apply_edits_dev call
+ * with global tet ids; with fused = 1 it is one launch, and with
+ * sta_apply_edits_dev it can be captured once into a HIP graph. */
+sta_status sta_batch_build(int k, const double* const* x, const int64_t* n_nodes, const int32_t* const* tets,
+                           const int64_t* n_tets, const double* const* E, double nu, double rho, double dt,
+                           const uint8_t* const* mask0, void* stream, sta_ctx** out);
+
+/* Per-mesh offsets of a batched context (k+1 entries each: node, tet, CSR
+ * row and value offsets; entry k is the total).  A context from
+ * sta_build_pattern is a batch of one. */
+sta_status sta_batch_offsets(const sta_ctx* ctx, int* k, int64_t* node_off, int64_t* tet_off, int64_t* row_off,
+                             int64_t* nnz_off, int64_t capacity);
 
 /* Synchronise `stream`, return and clear the first error the device
  * recorded (STA_ERANGE, STA_EDUP, STA_EDEGENERATE), else STA_OK. */

@@ -113,11 +113,16 @@ hipError_t timed(sta_ctx* c, int kernel, hipStream_t s, F&& launch)
 
 }  // namespace
 
-extern "C" {
+namespace sta {
 
-sta_status sta_build_pattern(const double* x, int64_t n_nodes, const int32_t* tets, int64_t n_tets,
-                             const double* E, double nu, double rho, double dt, const uint8_t* mask0,
-                             void* stream, sta_ctx** out)
+std::string& build_error()
+{
+    return g_build_err;
+}
+
+sta_status build_context(const double* x, int64_t n_nodes, const int32_t* tets, int64_t n_tets, const double* E,
+                         double nu, double rho, double dt, const uint8_t* mask0, void* stream,
+                         const std::vector<int64_t>& node_off, const std::vector<int64_t>& tet_off, sta_ctx** out)
 {
     g_build_err.clear();
     if (!out)
@@ -203,7 +208,7 @@ sta_status sta_build_pattern(const double* x, int64_t n_nodes, const int32_t* te
     ALLOC(bstamp, nb);
     ALLOC(rec, 10 * n_tets);
     ALLOC(undo, n_tets);
-    ALLOC(wg_err, 16 * n_tets / 256 + 2);
+    ALLOC(wg_err, 16 * n_tets / 256 + 4096);
     ALLOC(ctl, 1);
 #undef ALLOC
     if (e != hipSuccess) {
@@ -269,7 +274,7 @@ sta_status sta_build_pattern(const double* x, int64_t n_nodes, const int32_t* te
     v.ctl = ctl;
 
     if (e == hipSuccess) e = launch_element(v, s);
-    if (e == hipSuccess) e = launch_reduce_all(v, s);
+    if (e == hipSuccess) e = launch_reduce_all(v, c->rebuild_map, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     int32_t bits = 0;
     if (e == hipSuccess) e = hipMemcpy(&bits, &ctl->err, sizeof(int32_t), hipMemcpyDeviceToHost);
@@ -283,8 +288,62 @@ sta_status sta_build_pattern(const double* x, int64_t n_nodes, const int32_t* te
         delete c;
         return fail(nullptr, STA_EDEGENERATE, "a candidate tet has zero volume (det == 0)");
     }
+    c->node_off = node_off;
+    c->tet_off = tet_off;
+    c->nnz_off.resize(node_off.size());
+    for (size_t j = 0; j < node_off.size(); ++j)
+        c->nnz_off[j] = P.rowptr[3 * node_off[j]];
     *out = c;
     return STA_OK;
+}
+
+}  // namespace sta
+
+namespace {
+
+// One frame: two launches, or one persistent launch.
+sta_status run_frame(sta_ctx* ctx, const int32_t* ids, const uint8_t* states, int32_t n_host, const int32_t* n_dev,
+                     hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    if (ctx->fused) {
+        if (ctx->frame_max_grid <= 0) {
+            e = frame_max_grid(ctx->stream_map, ctx->device, &ctx->frame_max_grid);
+            if (e != hipSuccess)
+                return hip_fail(ctx, e, "occupancy query");
+            if (ctx->frame_max_grid <= 0)
+                return fail(ctx, STA_EINVAL, "fused frame kernel cannot be resident");
+        }
+        const int grid = frame_grid_for(ctx->stream_map, n_host, ctx->frame_max_grid, ctx->frame_grid_cap);
+        e = timed(ctx, STA_KERNEL_FRAME, s,
+                  [&] { return launch_frame(ctx->v, ctx->stream_map, grid, ids, states, n_host, n_dev, s); });
+    } else {
+        e = timed(ctx, STA_KERNEL_EDITS, s,
+                  [&] { return launch_edit_phase(ctx->v, ids, states, n_host, n_dev, s); });
+        if (e == hipSuccess)
+            e = timed(ctx, STA_KERNEL_TOUCHED, s,
+                      [&] { return launch_touched_phase(ctx->v, ctx->stream_map, ids, n_host, n_dev, s); });
+    }
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "frame launch");
+    return STA_OK;
+}
+
+bool valid_map(int qd, int qo)
+{
+    return (qd == 1 || qd == 4 || qd == 16) && (qo == 1 || qo == 4);
+}
+
+}  // namespace
+
+extern "C" {
+
+sta_status sta_build_pattern(const double* x, int64_t n_nodes, const int32_t* tets, int64_t n_tets,
+                             const double* E, double nu, double rho, double dt, const uint8_t* mask0,
+                             void* stream, sta_ctx** out)
+{
+    return sta::build_context(x, n_nodes, tets, n_tets, E, nu, rho, dt, mask0, stream, {0, n_nodes},
+                              {0, n_tets}, out);
 }
 
 sta_status sta_full_rebuild(sta_ctx* ctx, void* stream)
@@ -294,7 +353,7 @@ sta_status sta_full_rebuild(sta_ctx* ctx, void* stream)
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = timed(ctx, STA_KERNEL_ELEMENT, s, [&] { return launch_element(ctx->v, s); });
     if (e == hipSuccess)
-        e = timed(ctx, STA_KERNEL_REDUCE, s, [&] { return launch_reduce_all(ctx->v, s); });
+        e = timed(ctx, STA_KERNEL_REDUCE, s, [&] { return launch_reduce_all(ctx->v, ctx->rebuild_map, s); });
     if (e != hipSuccess)
         return hip_fail(ctx, e, "full_rebuild launch");
     ctx->stale = false;
@@ -312,15 +371,7 @@ sta_status sta_apply_edits(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* 
         return fail(ctx, STA_EINVAL, "NULL edit array");
     if (ctx->stale)
         return fail(ctx, STA_ESTALE, "parameters changed: call sta_full_rebuild before sta_apply_edits");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const int32_t n = (int32_t)n_edits;
-    hipError_t e = timed(ctx, STA_KERNEL_EDITS, s,
-                         [&] { return launch_edit_phase(ctx->v, ids_dev, states_dev, n, nullptr, s); });
-    if (e == hipSuccess)
-        e = timed(ctx, STA_KERNEL_TOUCHED, s, [&] { return launch_touched_phase(ctx->v, ids_dev, n, nullptr, s); });
-    if (e != hipSuccess)
-        return hip_fail(ctx, e, "apply_edits launch");
-    return STA_OK;
+    return run_frame(ctx, ids_dev, states_dev, (int32_t)n_edits, nullptr, static_cast<hipStream_t>(stream));
 }
 
 sta_status sta_apply_edits_dev(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* states_dev, const int32_t* n_dev,
@@ -334,15 +385,7 @@ sta_status sta_apply_edits_dev(sta_ctx* ctx, const int32_t* ids_dev, const uint8
         return fail(ctx, STA_EINVAL, "NULL edit array or count");
     if (ctx->stale)
         return fail(ctx, STA_ESTALE, "parameters changed: call sta_full_rebuild before sta_apply_edits_dev");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const int32_t cap = (int32_t)capacity;
-    hipError_t e = timed(ctx, STA_KERNEL_EDITS, s,
-                         [&] { return launch_edit_phase(ctx->v, ids_dev, states_dev, cap, n_dev, s); });
-    if (e == hipSuccess)
-        e = timed(ctx, STA_KERNEL_TOUCHED, s, [&] { return launch_touched_phase(ctx->v, ids_dev, cap, n_dev, s); });
-    if (e != hipSuccess)
-        return hip_fail(ctx, e, "apply_edits_dev launch");
-    return STA_OK;
+    return run_frame(ctx, ids_dev, states_dev, (int32_t)capacity, n_dev, static_cast<hipStream_t>(stream));
 }
 
 const double* sta_values_ptr(const sta_ctx* ctx)
@@ -511,6 +554,13 @@ sta_status sta_status_sync(sta_ctx* ctx, void* stream)
     }
     if (e != hipSuccess)
         return hip_fail(ctx, e, "status sync");
+    if (bits & ERR_TIMEOUT) {
+        const uint32_t zero2[2] = {0u, 0u};
+        (void)hipMemcpy(&ctx->v.ctl->bar_count, zero2, sizeof(zero2), hipMemcpyHostToDevice);
+        ctx->errmsg = "a fused frame's grid barrier timed out (GPU shared with other work); "
+                      "the frame is incomplete, call sta_full_rebuild";
+        return STA_ETIMEOUT;
+    }
     const sta_status st = device_errors(bits);
     if (st == STA_ERANGE)
         ctx->errmsg = "an edit named a tet id outside [0, n_tets) or a state other than 0/1; frame rolled back";
@@ -519,6 +569,52 @@ sta_status sta_status_sync(sta_ctx* ctx, void* stream)
     else if (st == STA_EDEGENERATE)
         ctx->errmsg = "an element with det == 0 was assembled";
     return st;
+}
+
+sta_status sta_set_config(sta_ctx* ctx, int fused, int rebuild_qd, int rebuild_qo, int stream_qd, int stream_qo,
+                          int grid_cap)
+{
+    if (!ctx || (fused != 0 && fused != 1) || !valid_map(rebuild_qd, rebuild_qo) || !valid_map(stream_qd, stream_qo) ||
+        grid_cap < 0)
+        return STA_EINVAL;
+    if (stream_qd != ctx->stream_map.qd || stream_qo != ctx->stream_map.qo)
+        ctx->frame_max_grid = 0;
+    ctx->fused = fused;
+    ctx->rebuild_map = MapConfig{rebuild_qd, rebuild_qo};
+    ctx->stream_map = MapConfig{stream_qd, stream_qo};
+    ctx->frame_grid_cap = grid_cap;
+    return STA_OK;
+}
+
+sta_status sta_get_config(const sta_ctx* ctx, int* out6)
+{
+    if (!ctx || !out6)
+        return STA_EINVAL;
+    out6[0] = ctx->fused;
+    out6[1] = ctx->rebuild_map.qd;
+    out6[2] = ctx->rebuild_map.qo;
+    out6[3] = ctx->stream_map.qd;
+    out6[4] = ctx->stream_map.qo;
+    out6[5] = ctx->frame_grid_cap;
+    return STA_OK;
+}
+
+sta_status sta_batch_offsets(const sta_ctx* ctx, int* k, int64_t* node_off, int64_t* tet_off, int64_t* row_off,
+                             int64_t* nnz_off, int64_t capacity)
+{
+    if (!ctx || !k)
+        return STA_EINVAL;
+    const int64_t nk = (int64_t)ctx->node_off.size() - 1;
+    *k = (int)nk;
+    if (capacity < nk + 1)
+        return capacity == 0 ? STA_OK : STA_EINVAL;
+    for (int64_t j = 0; j <= nk; ++j) {
+        if (node_off) node_off[j] = ctx->node_off[j];
+        if (tet_off) tet_off[j] = ctx->tet_off[j];
+        if (row_off) row_off[j] = 3 * ctx->node_off[j];
+        if (nnz_off) nnz_off[j] = ctx->nnz_off[j];
+    }
+    return STA_OK;
 }
 
 sta_status sta_adjoint(sta_ctx* ctx, const double* gA_dev, double* g_logE_dev, double* g_x_dev, void* stream)

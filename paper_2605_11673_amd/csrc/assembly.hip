@@ -29,7 +29,6 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kXcds = 8;
-constexpr int kLanesPerEdit = 78;  // phase 2: 4 diagonal blocks x 6 values + 6 off-diagonal blocks x 9 values
 constexpr int kEditLanes = 16;     // phase 1: one lane per block slot (10 used), power of two
 
 // Workgroups are dispatched round-robin over the 8 XCDs.  Remap so that each
@@ -175,42 +174,74 @@ __device__ __forceinline__ void zero_element(const DevView& v, const int* pos)
 }
 
 // The canonical sum of value vi of one block: +0.0 plus the segment's terms
-// in ascending tet id.  Loads are issued CH at a time so that a whole
-// segment (up to CH terms) is in flight at once; padding terms are +0.0.
-template <int CH>
-__device__ __forceinline__ double seg_sum(const double* __restrict__ c, int stride, int vi, int k0, int k1)
+// in ascending tet id.  Q lanes share one value ("slot mapping": Q = 1
+// thread-, 4 quad-, 16 wave-sixteenth-per-slot): lane q of the group loads
+// terms q, q+Q, q+2Q, ... CH at a time (padding terms are +0.0), then every
+// lane of the group adds all terms in ascending order, taking each from the
+// lane that holds it.  The additions are the same whatever Q is, so the
+// result is bit-identical across mappings.  src0: wave lane of the group's
+// lane 0; groups of Q lanes never straddle a wave.
+template <int Q, int CH>
+__device__ __forceinline__ double seg_sum(const double* __restrict__ c, int stride, int vi, int k0, int k1, int q,
+                                          int src0)
 {
     double acc = 0.0;
-    for (int base = k0; base < k1; base += CH) {
+    for (int base = k0; base < k1; base += Q * CH) {
         double t[CH];
 #pragma unroll
-        for (int j = 0; j < CH; ++j)
-            t[j] = (base + j < k1) ? c[(size_t)(base + j) * stride + vi] : 0.0;
+        for (int j = 0; j < CH; ++j) {
+            const int k = base + q + j * Q;
+            t[j] = k < k1 ? c[(size_t)k * stride + vi] : 0.0;
+        }
+        if (Q == 1) {
 #pragma unroll
-        for (int j = 0; j < CH; ++j)
-            acc = acc + t[j];
+            for (int j = 0; j < CH; ++j)
+                acc = acc + t[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < CH; ++j)
+#pragma unroll
+                for (int l = 0; l < Q; ++l)
+                    acc = acc + __shfl(t[j], src0 + l, 64);
+        }
     }
     return acc;
 }
+
+// Terms held per lane per chunk: about 32 loads in flight per diagonal value.
+template <int Q>
+struct DiagChunk {
+    static constexpr int CH = Q == 1 ? 32 : (Q == 4 ? 8 : 2);
+};
+template <int Q>
+struct OffChunk {
+    static constexpr int CH = Q == 1 ? 8 : 2;
+};
 
 __device__ __constant__ int kDiagP[6] = {0, 0, 0, 1, 1, 2};
 __device__ __constant__ int kDiagQ[6] = {0, 1, 2, 1, 2, 2};
 
 // Recompute value vi (0..5 unique diagonal values, 0..8 off-diagonal) of the
 // block described by d and write it (and its mirror) into the CSR values.
-__device__ __forceinline__ void block_value(const DevView& v, const BlockDesc& d, int vi)
+// All QD (or QO) lanes of the group call this; lane q == 0 writes.
+template <int QD, int QO>
+__device__ __forceinline__ void block_value(const DevView& v, const BlockDesc& d, int vi, int q, int src0)
 {
     if (d.kind == 0) {
-        const double acc = seg_sum<32>(v.cd, 6, vi, d.k0, d.k1);
-        const int p = kDiagP[vi], q = kDiagQ[vi];
-        v.values[d.up + p * d.rl + q] = acc;
-        if (p != q)
-            v.values[d.up + q * d.rl + p] = acc;
+        const double acc = seg_sum<QD, DiagChunk<QD>::CH>(v.cd, 6, vi, d.k0, d.k1, q, src0);
+        if (q == 0) {
+            const int p = kDiagP[vi], r = kDiagQ[vi];
+            v.values[d.up + p * d.rl + r] = acc;
+            if (p != r)
+                v.values[d.up + r * d.rl + p] = acc;
+        }
     } else {
-        const double acc = seg_sum<8>(v.co, 9, vi, d.k0, d.k1);
-        const int p = vi / 3, q = vi - 3 * (vi / 3);
-        v.values[d.up + p * d.rl + q] = acc;
-        v.values[d.lo + q * d.rlj + p] = acc;
+        const double acc = seg_sum<QO, OffChunk<QO>::CH>(v.co, 9, vi, d.k0, d.k1, q, src0);
+        if (q == 0) {
+            const int p = vi / 3, r = vi - 3 * (vi / 3);
+            v.values[d.up + p * d.rl + r] = acc;
+            v.values[d.lo + r * d.rlj + p] = acc;
+        }
     }
 }
 
@@ -258,25 +289,30 @@ __global__ __launch_bounds__(kBlock) void k_element(DevView v)
         zero_element(v, pos);
 }
 
-// Lanes: 6 per diagonal block, then 9 per off-diagonal block.
-__global__ __launch_bounds__(kBlock) void k_reduce_all(DevView v)
+// Lanes: 6*QD per diagonal block (section padded to whole waves), then 9*QO
+// per off-diagonal block.
+template <int QD, int QO>
+__global__ __launch_bounds__(kBlock) void k_reduce_all(DevView v, int64_t diag_lanes)
 {
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t t = (int64_t)wg * kBlock + threadIdx.x;
-    const int64_t nd6 = (int64_t)v.nd * 6;
-    int b, vi;
-    if (t < nd6) {
-        b = (int)(t / 6);
-        vi = (int)(t - 6 * (int64_t)b);
-    } else {
-        const int64_t u = t - nd6;
-        if (u >= (int64_t)v.no * 9)
+    const int lane = threadIdx.x & 63;
+    if (t < diag_lanes) {
+        const int b = (int)(t / (6 * QD));
+        if (b >= v.nd)
             return;
-        const int o = (int)(u / 9);
-        vi = (int)(u - 9 * (int64_t)o);
-        b = v.nd + o;
+        const int rem = (int)(t - (int64_t)b * (6 * QD));
+        const int q = rem % QD;
+        block_value<QD, QO>(v, load_desc(v.desc + b), rem / QD, q, lane - q);
+    } else {
+        const int64_t u = t - diag_lanes;
+        const int o = (int)(u / (9 * QO));
+        if (o >= v.no)
+            return;
+        const int rem = (int)(u - (int64_t)o * (9 * QO));
+        const int q = rem % QO;
+        block_value<QD, QO>(v, load_desc(v.desc + v.nd + o), rem / QO, q, lane - q);
     }
-    block_value(v, load_desc(v.desc + b), vi);
 }
 
 // ---------------------------------------------------------------------------
@@ -369,126 +405,99 @@ __device__ __forceinline__ int frame_count(int32_t n_host, const int32_t* n_dev,
     return n;
 }
 
-// Phase 1, 16 lanes per edit (lane r < 10 owns block slot r).  Validate the
-// edit; lane 0 takes the tet's stamp (a second edit of the same tet in this
-// frame finds it taken: duplicate) and reads its mask bit.  If the state
-// changes, each slot lane claims its block (first claimant wins; the claim
-// record carries the block descriptor), the owner flips the mask bit and the
-// slot lanes rewrite the tet's 78 contribution slots (element matrix on
-// activation, zeros on deactivation).  Each workgroup writes its error bits
-// to its own byte, so no global word needs resetting between frames.
-__global__ __launch_bounds__(kBlock) void k_edits(DevView v, const int32_t* __restrict__ ids,
-                                                  const uint8_t* __restrict__ states, int32_t n_host,
-                                                  const int32_t* __restrict__ n_dev)
+// Phase 1 for lane r of edit i (16 lanes per edit; lane r < 10 owns block
+// slot r).  Validate the edit; lane 0 takes the tet's stamp (a second edit of
+// the same tet in this frame finds it taken: duplicate) and reads its mask
+// bit.  If the state changes, each slot lane claims its block (first
+// claimant wins; the claim record carries the block descriptor), the owner
+// flips the mask bit and the slot lanes rewrite the tet's 78 contribution
+// slots (element matrix on activation, zeros on deactivation).  Returns the
+// lane's error bits.  All 16 lanes of the edit must call it together.
+__device__ __forceinline__ int edit_lane(const DevView& v, const int32_t* __restrict__ ids,
+                                         const uint8_t* __restrict__ states, int i, int r)
 {
-    __shared__ int s_bits;
-    if (threadIdx.x == 0)
-        s_bits = 0;
-    __syncthreads();
-    bool bad_n;
-    const int n = frame_count(n_host, n_dev, bad_n);
-    const int gt = blockIdx.x * kBlock + threadIdx.x;
-    const int i = gt / kEditLanes;
-    const int r = gt - i * kEditLanes;
-    int bits = (bad_n && gt == 0) ? ERR_RANGE : 0;
-    if (i < n) {
-        BlockDesc* rec = v.rec + 10 * (size_t)i;
-        const int id = ids[i];
-        const unsigned st = states[i];
-        if (id < 0 || id >= v.n_tets || st > 1u) {
-            if (r == 0) {
-                bits |= ERR_RANGE;
-                v.undo[i] = 0xFF;
-            }
-            if (r < 10)
-                store_desc(rec + r, empty_desc());
-        } else {
-            int eb = 0, ep = 0;
-            if (r < 10) {
-                eb = v.e2b[10 * (size_t)id + r];
-                ep = v.e2p[10 * (size_t)id + r];
-            }
-            const uint8_t prev = v.mask[id];
-            int owner = 1;
-            if (r == 0)
-                owner = atomicExch(&v.estamp[id], 1u) == 0u ? 1 : 0;
-            const int lane = threadIdx.x & 63;
-            owner = __shfl(owner, lane & ~(kEditLanes - 1), 64);
-            const bool change = prev != st;
-            if (r < 10) {
-                BlockDesc d = empty_desc();
-                if (change) {
-                    const BlockDesc bd = load_desc(v.desc + eb);
-                    if (atomicExch(&v.bstamp[eb], 1u) == 0u)
-                        d = bd;
-                }
-                store_desc(rec + r, d);
-            }
-            if (!owner) {
-                if (r == 0)
-                    bits |= ERR_DUP;
-            } else if (change) {
-                if (r == 0)
-                    v.mask[id] = (uint8_t)st;
-                if (r < 10)
-                    store_slot(v, id, v.T[id], r, ep, st != 0u);
-            }
-            if (r == 0)
-                v.undo[i] = (owner && change) ? prev : (uint8_t)0xFF;
+    BlockDesc* rec = v.rec + 10 * (size_t)i;
+    const int id = ids[i];
+    const unsigned st = states[i];
+    if (id < 0 || id >= v.n_tets || st > 1u) {
+        if (r < 10)
+            store_desc(rec + r, empty_desc());
+        if (r == 0) {
+            v.undo[i] = 0xFF;
+            return ERR_RANGE;
         }
+        return 0;
     }
-    if (bits)
-        atomicOr(&s_bits, bits);
-    __syncthreads();
-    if (threadIdx.x == 0)
-        v.wg_err[blockIdx.x] = (uint8_t)s_bits;
+    int eb = 0, ep = 0;
+    if (r < 10) {
+        eb = v.e2b[10 * (size_t)id + r];
+        ep = v.e2p[10 * (size_t)id + r];
+    }
+    const uint8_t prev = v.mask[id];
+    int owner = 1;
+    if (r == 0)
+        owner = atomicExch(&v.estamp[id], 1u) == 0u ? 1 : 0;
+    owner = __shfl(owner, (threadIdx.x & 63) & ~(kEditLanes - 1), 64);
+    const bool change = prev != st;
+    if (r < 10) {
+        BlockDesc d = empty_desc();
+        if (change) {
+            const BlockDesc bd = load_desc(v.desc + eb);
+            if (atomicExch(&v.bstamp[eb], 1u) == 0u)
+                d = bd;
+        }
+        store_desc(rec + r, d);
+    }
+    int bits = 0;
+    if (!owner) {
+        if (r == 0)
+            bits = ERR_DUP;
+    } else if (change) {
+        if (r == 0)
+            v.mask[id] = (uint8_t)st;
+        if (r < 10)
+            store_slot(v, id, v.T[id], r, ep, st != 0u);
+    }
+    if (r == 0)
+        v.undo[i] = (owner && change) ? prev : (uint8_t)0xFF;
+    return bits;
 }
 
-// Phase 2: 78 lanes per edit (4 diagonal blocks x 6 values, 6 off-diagonal
-// blocks x 9 values).  Every workgroup first ORs the edit workgroups' error
-// bytes.  Without an error a lane re-sums its value if the edit claimed the
-// block; with one, lane 0 of each edit undoes its mask flip and slot rewrite.
-// Either way the frame's stamps are cleared for the next frame.
-__global__ __launch_bounds__(kBlock) void k_touched(DevView v, const int32_t* __restrict__ ids, int32_t n_host,
-                                                    const int32_t* __restrict__ n_dev)
+// Lanes per edit in phase 2: 4 diagonal blocks x 6 values x QD lanes, then
+// 6 off-diagonal blocks x 9 values x QO lanes, rounded up to 16 so that the
+// lane groups of every edit stay aligned inside a wave.
+template <int QD, int QO>
+struct Phase2 {
+    static constexpr int kDiag = 24 * QD;
+    static constexpr int kLanes = (24 * QD + 54 * QO + 15) / 16 * 16;
+};
+
+// Phase 2 for lane r of edit i.  fe: the frame's error bits.  Without an
+// error the lane group re-sums its value if the edit claimed the block; with
+// one, lane 0 undoes the edit's mask flip and slot rewrite.  Either way the
+// frame's stamps are cleared for the next frame.
+template <int QD, int QO>
+__device__ __forceinline__ void touched_lane(const DevView& v, const int32_t* __restrict__ ids, int fe, int i, int r)
 {
-    __shared__ int s_bits;
-    if (threadIdx.x == 0)
-        s_bits = 0;
-    __syncthreads();
-    bool bad_n;
-    const int n = frame_count(n_host, n_dev, bad_n);
-    const int g_edits = n > 0 ? (n * kEditLanes + kBlock - 1) / kBlock : 1;
-    int bits = 0;
-    for (int w = threadIdx.x; w < g_edits; w += kBlock)
-        bits |= v.wg_err[w];
-    if (bits)
-        atomicOr(&s_bits, bits);
-    __syncthreads();
-    const int fe = s_bits;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        v.ctl->frame_err = fe;
-        v.ctl->last_n = n;
-        if (fe)
-            atomicOr(&v.ctl->err, fe);
-    }
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int i = (int)(t / kLanesPerEdit);
-    const int r = (int)(t - (int64_t)i * kLanesPerEdit);
-    if (i >= n)
-        return;
-    int j, vi;
-    if (r < 24) {
-        j = r / 6;
-        vi = r - 6 * j;
+    int j, vi, q;
+    if (r < Phase2<QD, QO>::kDiag) {
+        j = r / (6 * QD);
+        const int rem = r - j * (6 * QD);
+        vi = rem / QD;
+        q = rem - vi * QD;
     } else {
-        j = 4 + (r - 24) / 9;
-        vi = (r - 24) - 9 * (j - 4);
+        const int rr = r - Phase2<QD, QO>::kDiag;
+        if (rr >= 54 * QO)
+            return;
+        j = 4 + rr / (9 * QO);
+        const int rem = rr - (j - 4) * (9 * QO);
+        vi = rem / QO;
+        q = rem - vi * QO;
     }
     const BlockDesc d = load_desc(v.rec + 10 * (size_t)i + j);
     if (!fe && d.kind >= 0)
-        block_value(v, d, vi);
-    if (vi == 0 && d.kind >= 0)
+        block_value<QD, QO>(v, d, vi, q, (threadIdx.x & 63) - q);
+    if (vi == 0 && q == 0 && d.kind >= 0)
         v.bstamp[d.block] = 0u;
     if (r == 0) {
         const int id = ids[i];
@@ -498,8 +507,8 @@ __global__ __launch_bounds__(kBlock) void k_touched(DevView v, const int32_t* __
             if (fe && u != 0xFF) {
                 int ep[10];
 #pragma unroll
-                for (int q = 0; q < 10; ++q)
-                    ep[q] = v.e2p[10 * (size_t)id + q];
+                for (int k = 0; k < 10; ++k)
+                    ep[k] = v.e2p[10 * (size_t)id + k];
                 v.mask[id] = u;
                 if (u)
                     store_element(v, id, v.T[id], ep);
@@ -507,6 +516,141 @@ __global__ __launch_bounds__(kBlock) void k_touched(DevView v, const int32_t* __
                     zero_element(v, ep);
             }
         }
+    }
+}
+
+// Workgroup-wide OR of error bits.
+__device__ __forceinline__ int block_or(int bits, int* s_bits)
+{
+    if (threadIdx.x == 0)
+        *s_bits = 0;
+    __syncthreads();
+    if (bits)
+        atomicOr(s_bits, bits);
+    __syncthreads();
+    return *s_bits;
+}
+
+// OR of the first g error bytes of the edit phase.
+__device__ __forceinline__ int frame_error(const DevView& v, int g, int* s_bits)
+{
+    int bits = 0;
+    for (int w = threadIdx.x; w < g; w += kBlock)
+        bits |= v.wg_err[w];
+    return block_or(bits, s_bits);
+}
+
+__device__ __forceinline__ void publish_frame(const DevView& v, int fe, int n)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        v.ctl->frame_err = fe;
+        v.ctl->last_n = n;
+        if (fe)
+            atomicOr(&v.ctl->err, fe);
+    }
+}
+
+// Phase 1 as its own kernel: one 16-lane group per edit.  Each workgroup
+// writes its error bits to its own byte, so nothing needs resetting.
+__global__ __launch_bounds__(kBlock) void k_edits(DevView v, const int32_t* __restrict__ ids,
+                                                  const uint8_t* __restrict__ states, int32_t n_host,
+                                                  const int32_t* __restrict__ n_dev)
+{
+    __shared__ int s_bits;
+    bool bad_n;
+    const int n = frame_count(n_host, n_dev, bad_n);
+    const int gt = blockIdx.x * kBlock + threadIdx.x;
+    const int i = gt / kEditLanes;
+    int bits = (bad_n && gt == 0) ? ERR_RANGE : 0;
+    if (i < n)
+        bits |= edit_lane(v, ids, states, i, gt - i * kEditLanes);
+    bits = block_or(bits, &s_bits);
+    if (threadIdx.x == 0)
+        v.wg_err[blockIdx.x] = (uint8_t)bits;
+}
+
+// Phase 2 as its own kernel.
+template <int QD, int QO>
+__global__ __launch_bounds__(kBlock) void k_touched(DevView v, const int32_t* __restrict__ ids, int32_t n_host,
+                                                    const int32_t* __restrict__ n_dev)
+{
+    __shared__ int s_bits;
+    bool bad_n;
+    const int n = frame_count(n_host, n_dev, bad_n);
+    const int fe = frame_error(v, n > 0 ? (n * kEditLanes + kBlock - 1) / kBlock : 1, &s_bits);
+    publish_frame(v, fe, n);
+    constexpr int L = Phase2<QD, QO>::kLanes;
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int i = (int)(t / L);
+    if (i < n)
+        touched_lane<QD, QO>(v, ids, fe, i, (int)(t - (int64_t)i * L));
+}
+
+// Grid-wide barrier for a co-resident grid (the host sizes the grid from the
+// occupancy so that every workgroup is resident).  The spin is bounded: a
+// grid that is not co-resident reports ERR_TIMEOUT instead of hanging.
+constexpr unsigned kBarrierSpinLimit = 1u << 24;
+
+__device__ __forceinline__ bool grid_barrier(Ctl* ctl, unsigned G, int* s_ok)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned gen = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const unsigned arrived = atomicAdd(&ctl->bar_count, 1u);
+        if (arrived == G - 1) {
+            __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            __hip_atomic_fetch_add(&ctl->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > kBarrierSpinLimit) {
+                    ok = 0;
+                    atomicOr(&ctl->err, ERR_TIMEOUT);
+                    break;
+                }
+            }
+        }
+        __threadfence();
+        *s_ok = ok;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+// The whole frame in one persistent launch: phase 1 over the edits, grid
+// barrier, phase 2 over the claimed blocks (grid-stride loops; lane groups
+// stay aligned because the stride is a multiple of the workgroup size).
+template <int QD, int QO>
+__global__ __launch_bounds__(kBlock) void k_frame(DevView v, const int32_t* __restrict__ ids,
+                                                  const uint8_t* __restrict__ states, int32_t n_host,
+                                                  const int32_t* __restrict__ n_dev)
+{
+    __shared__ int s_bits;
+    __shared__ int s_ok;
+    bool bad_n;
+    const int n = frame_count(n_host, n_dev, bad_n);
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int bits = (bad_n && t0 == 0) ? ERR_RANGE : 0;
+    for (int64_t t = t0; t < (int64_t)n * kEditLanes; t += stride) {
+        const int i = (int)(t / kEditLanes);
+        bits |= edit_lane(v, ids, states, i, (int)(t - (int64_t)i * kEditLanes));
+    }
+    bits = block_or(bits, &s_bits);
+    if (threadIdx.x == 0)
+        v.wg_err[blockIdx.x] = (uint8_t)bits;
+    if (!grid_barrier(v.ctl, gridDim.x, &s_ok))
+        return;
+    const int fe = frame_error(v, gridDim.x, &s_bits);
+    publish_frame(v, fe, n);
+    constexpr int L = Phase2<QD, QO>::kLanes;
+    for (int64_t t = t0; t < (int64_t)n * L; t += stride) {
+        const int i = (int)(t / L);
+        touched_lane<QD, QO>(v, ids, fe, i, (int)(t - (int64_t)i * L));
     }
 }
 
@@ -539,29 +683,91 @@ hipError_t launch_element(const DevView& v, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_all(const DevView& v, hipStream_t s)
+#define STA_MAPPINGS(X) X(1, 1) X(1, 4) X(4, 1) X(4, 4) X(16, 1) X(16, 4)
+
+hipError_t launch_reduce_all(const DevView& v, const MapConfig& m, hipStream_t s)
 {
-    const int64_t threads = (int64_t)v.nd * 6 + (int64_t)v.no * 9;
-    if (threads == 0)
+    const int64_t diag_lanes = ((int64_t)v.nd * 6 * m.qd + 63) / 64 * 64;
+    const int64_t threads = diag_lanes + (int64_t)v.no * 9 * m.qo;
+    if (v.nd + v.no == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_all, dim3(blocks_for(threads)), dim3(kBlock), 0, s, v);
-    return hipGetLastError();
+#define LAUNCH(QD, QO)                                                                                   \
+    if (m.qd == QD && m.qo == QO) {                                                                      \
+        hipLaunchKernelGGL((k_reduce_all<QD, QO>), dim3(blocks_for(threads)), dim3(kBlock), 0, s, v, diag_lanes); \
+        return hipGetLastError();                                                                        \
+    }
+    STA_MAPPINGS(LAUNCH)
+#undef LAUNCH
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_edit_phase(const DevView& v, const int32_t* ids, const uint8_t* states, int32_t n_host,
                              const int32_t* n_dev, hipStream_t s)
 {
     // an empty list still runs one workgroup of each phase: they record the frame (count 0)
-    hipLaunchKernelGGL(k_edits, dim3(n_host > 0 ? blocks_for((int64_t)n_host * kEditLanes) : 1u), dim3(kBlock), 0, s, v, ids, states, n_host, n_dev);
+    hipLaunchKernelGGL(k_edits, dim3(n_host > 0 ? blocks_for((int64_t)n_host * kEditLanes) : 1u), dim3(kBlock), 0,
+                       s, v, ids, states, n_host, n_dev);
     return hipGetLastError();
 }
 
-hipError_t launch_touched_phase(const DevView& v, const int32_t* ids, int32_t n_host, const int32_t* n_dev,
-                                hipStream_t s)
+hipError_t launch_touched_phase(const DevView& v, const MapConfig& m, const int32_t* ids, int32_t n_host,
+                                const int32_t* n_dev, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_touched, dim3(n_host > 0 ? blocks_for((int64_t)n_host * kLanesPerEdit) : 1u), dim3(kBlock), 0, s, v, ids,
-                       n_host, n_dev);
-    return hipGetLastError();
+#define LAUNCH(QD, QO)                                                                                      \
+    if (m.qd == QD && m.qo == QO) {                                                                         \
+        const int64_t lanes = (int64_t)n_host * Phase2<QD, QO>::kLanes;                                     \
+        hipLaunchKernelGGL((k_touched<QD, QO>), dim3(n_host > 0 ? blocks_for(lanes) : 1u), dim3(kBlock), 0, s, v, \
+                           ids, n_host, n_dev);                                                             \
+        return hipGetLastError();                                                                           \
+    }
+    STA_MAPPINGS(LAUNCH)
+#undef LAUNCH
+    return hipErrorInvalidValue;
+}
+
+hipError_t frame_max_grid(const MapConfig& m, int device, int* max_grid)
+{
+    int cus = 0, per_cu = 0;
+    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess)
+        return e;
+#define OCC(QD, QO)                                                                                        \
+    if (m.qd == QD && m.qo == QO)                                                                          \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)&k_frame<QD, QO>, kBlock, 0);
+    STA_MAPPINGS(OCC)
+#undef OCC
+    if (e != hipSuccess)
+        return e;
+    *max_grid = per_cu * cus;
+    return hipSuccess;
+}
+
+int frame_grid_for(const MapConfig& m, int32_t n_host, int max_grid, int grid_cap)
+{
+    int L = 16;
+#define LANES(QD, QO)                 \
+    if (m.qd == QD && m.qo == QO)     \
+        L = Phase2<QD, QO>::kLanes;
+    STA_MAPPINGS(LANES)
+#undef LANES
+    const int64_t want = n_host > 0 ? ((int64_t)n_host * L + kBlock - 1) / kBlock : 1;
+    int64_t g = want < max_grid ? want : max_grid;
+    if (grid_cap > 0 && g > grid_cap)
+        g = grid_cap;
+    return (int)(g < 1 ? 1 : g);
+}
+
+hipError_t launch_frame(const DevView& v, const MapConfig& m, int grid, const int32_t* ids, const uint8_t* states,
+                        int32_t n_host, const int32_t* n_dev, hipStream_t s)
+{
+#define LAUNCH(QD, QO)                                                                                        \
+    if (m.qd == QD && m.qo == QO) {                                                                           \
+        hipLaunchKernelGGL((k_frame<QD, QO>), dim3(grid), dim3(kBlock), 0, s, v, ids, states, n_host, n_dev); \
+        return hipGetLastError();                                                                             \
+    }
+    STA_MAPPINGS(LAUNCH)
+#undef LAUNCH
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_set_params(const DevView& v, const double* x_aos, const double* E, double* xs, double* ys,

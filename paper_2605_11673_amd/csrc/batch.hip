@@ -1,0 +1,291 @@
+// Batched contexts (many independent meshes in one context) and the
+// autotuner that picks the slot mapping and the frame execution mode.
+//
+// A batch of meshes is their disjoint union: node, tet, row and value ranges
+// are concatenated, so every kernel of the single-mesh path applies
+// unchanged, a frame over all meshes is one launch (or one graph replay),
+// and each mesh's values are bitwise what it would get alone (its blocks only
+// ever see its own tets, summed in the same order).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sta_internal.h"
+
+using namespace sta;
+
+namespace {
+
+sta_status tune_fail(sta_ctx* ctx, sta_status code, const std::string& msg)
+{
+    ctx->errmsg = msg;
+    return code;
+}
+
+struct Cfg {
+    int fused, rqd, rqo, sqd, sqo, cap;
+};
+
+std::string cache_key(const sta_ctx* ctx, int64_t n_edits)
+{
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "stafem-tune-v1 %lld %lld %lld %lld %lld %lld", (long long)ctx->n_nodes,
+                  (long long)ctx->n_tets, (long long)ctx->nnz, (long long)ctx->nd, (long long)ctx->no,
+                  (long long)n_edits);
+    return buf;
+}
+
+bool cache_lookup(const char* path, const std::string& key, Cfg& c)
+{
+    FILE* f = std::fopen(path, "r");
+    if (!f)
+        return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        const char* bar = std::strchr(line, '|');
+        if (!bar)
+            continue;
+        std::string k(line, bar - line);
+        while (!k.empty() && k.back() == ' ')
+            k.pop_back();
+        Cfg t;
+        if (k == key && std::sscanf(bar + 1, "%d %d %d %d %d %d", &t.fused, &t.rqd, &t.rqo, &t.sqd, &t.sqo, &t.cap) == 6) {
+            c = t;  // the last matching line wins
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const char* path, const std::string& key, const Cfg& c)
+{
+    FILE* f = std::fopen(path, "a");
+    if (!f)
+        return;
+    std::fprintf(f, "%s | %d %d %d %d %d %d\n", key.c_str(), c.fused, c.rqd, c.rqo, c.sqd, c.sqo, c.cap);
+    std::fclose(f);
+}
+
+double median(std::vector<float> v)
+{
+    std::sort(v.begin(), v.end());
+    return v.empty() ? 0.0 : v[v.size() / 2];
+}
+
+const int kMaps[6][2] = {{1, 1}, {1, 4}, {4, 1}, {4, 4}, {16, 1}, {16, 4}};
+
+}  // namespace
+
+extern "C" {
+
+sta_status sta_batch_build(int k, const double* const* x, const int64_t* n_nodes, const int32_t* const* tets,
+                           const int64_t* n_tets, const double* const* E, double nu, double rho, double dt,
+                           const uint8_t* const* mask0, void* stream, sta_ctx** out)
+{
+    build_error().clear();
+    if (!out || k < 1 || !x || !n_nodes || !tets || !n_tets || !E || !mask0) {
+        build_error() = "sta_batch_build: bad arguments";
+        return STA_EINVAL;
+    }
+    *out = nullptr;
+    std::vector<int64_t> noff(k + 1, 0), toff(k + 1, 0);
+    for (int j = 0; j < k; ++j) {
+        if (n_nodes[j] < 0 || n_tets[j] < 0) {
+            build_error() = "sta_batch_build: negative size";
+            return STA_EINVAL;
+        }
+        noff[j + 1] = noff[j] + n_nodes[j];
+        toff[j + 1] = toff[j] + n_tets[j];
+    }
+    if (noff[k] > INT32_MAX / 3 || toff[k] > INT32_MAX / 10) {
+        build_error() = "sta_batch_build: batch too large";
+        return STA_EINVAL;
+    }
+    std::vector<double> X((size_t)3 * noff[k]), Ev((size_t)toff[k]);
+    std::vector<int32_t> T((size_t)4 * toff[k]);
+    std::vector<uint8_t> M((size_t)toff[k]);
+    for (int j = 0; j < k; ++j) {
+        if ((n_nodes[j] > 0 && !x[j]) || (n_tets[j] > 0 && (!tets[j] || !E[j] || !mask0[j]))) {
+            build_error() = "sta_batch_build: NULL mesh array";
+            return STA_EINVAL;
+        }
+        if (n_nodes[j] > 0)
+            std::memcpy(&X[3 * noff[j]], x[j], sizeof(double) * 3 * n_nodes[j]);
+        for (int64_t t = 0; t < n_tets[j]; ++t)
+            for (int a = 0; a < 4; ++a) {
+                const int32_t v = tets[j][4 * t + a];
+                if (v < 0 || v >= n_nodes[j]) {
+                    build_error() = "sta_batch_build: mesh " + std::to_string(j) + " tet " + std::to_string(t) +
+                                    " has a vertex id out of range";
+                    return STA_EINVAL;
+                }
+                T[4 * (toff[j] + t) + a] = (int32_t)(v + noff[j]);
+            }
+        if (n_tets[j] > 0) {
+            std::memcpy(&Ev[toff[j]], E[j], sizeof(double) * n_tets[j]);
+            std::memcpy(&M[toff[j]], mask0[j], n_tets[j]);
+        }
+    }
+    return build_context(X.data(), noff[k], T.data(), toff[k], Ev.data(), nu, rho, dt, M.data(), stream, noff, toff,
+                         out);
+}
+
+sta_status sta_autotune(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* states_dev, int64_t n_edits, int reps,
+                        void* stream, char* report, int64_t report_len)
+{
+    if (!ctx || n_edits < 1 || n_edits > ctx->n_tets || !ids_dev || !states_dev)
+        return STA_EINVAL;
+    if (ctx->stale)
+        return tune_fail(ctx, STA_ESTALE, "parameters changed: call sta_full_rebuild before sta_autotune");
+    if (reps < 1)
+        reps = 7;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::string rep;
+    char line[256];
+    const char* cache = std::getenv("STA_TUNE_CACHE");
+    const std::string key = cache_key(ctx, n_edits);
+    Cfg best{};
+    auto finish = [&](sta_status st) {
+        if (report && report_len > 0) {
+            std::strncpy(report, rep.c_str(), (size_t)report_len - 1);
+            report[report_len - 1] = 0;
+        }
+        return st;
+    };
+    if (cache && cache_lookup(cache, key, best)) {
+        sta_status st = sta_set_config(ctx, best.fused, best.rqd, best.rqo, best.sqd, best.sqo, best.cap);
+        std::snprintf(line, sizeof line, "cached %s: fused %d rebuild %dx%d stream %dx%d cap %d\n", cache,
+                      best.fused, best.rqd, best.rqo, best.sqd, best.sqo, best.cap);
+        rep += line;
+        return finish(st);
+    }
+
+    // the inverse frame: same ids, each tet's current state
+    std::vector<int32_t> ids((size_t)n_edits);
+    std::vector<uint8_t> mask((size_t)ctx->n_tets), inv((size_t)n_edits);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess)
+        e = hipMemcpy(ids.data(), ids_dev, sizeof(int32_t) * n_edits, hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+        e = hipMemcpy(mask.data(), ctx->v.mask, ctx->n_tets, hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return tune_fail(ctx, STA_EHIP, "autotune copies failed");
+    {
+        std::vector<int32_t> sorted(ids);
+        std::sort(sorted.begin(), sorted.end());
+        if (sorted.front() < 0 || sorted.back() >= ctx->n_tets ||
+            std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+            return tune_fail(ctx, STA_EINVAL, "autotune needs a valid frame (ids in range, distinct)");
+    }
+    for (int64_t i = 0; i < n_edits; ++i)
+        inv[i] = mask[ids[i]];
+    uint8_t* inv_dev = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    e = hipMalloc(&inv_dev, n_edits);
+    if (e == hipSuccess)
+        e = hipMemcpy(inv_dev, inv.data(), n_edits, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipEventCreate(&a);
+    if (e == hipSuccess)
+        e = hipEventCreate(&b);
+    auto cleanup = [&]() {
+        if (inv_dev)
+            (void)hipFree(inv_dev);
+        if (a)
+            (void)hipEventDestroy(a);
+        if (b)
+            (void)hipEventDestroy(b);
+    };
+    if (e != hipSuccess) {
+        cleanup();
+        return tune_fail(ctx, STA_ENOMEM, "autotune workspace");
+    }
+    const Cfg saved{ctx->fused, ctx->rebuild_map.qd, ctx->rebuild_map.qo, ctx->stream_map.qd, ctx->stream_map.qo,
+                    ctx->frame_grid_cap};
+    const int saved_timing = ctx->timing;
+    ctx->timing = false;
+    sta_status st = STA_OK;
+
+    // 1. rebuild mapping
+    double best_t = 1e30;
+    best = saved;
+    for (auto& m : kMaps) {
+        sta_set_config(ctx, saved.fused, m[0], m[1], saved.sqd, saved.sqo, saved.cap);
+        std::vector<float> t;
+        for (int r = 0; r <= reps && st == STA_OK; ++r) {
+            float ms = 0.0f;
+            (void)hipEventRecord(a, s);
+            st = sta_full_rebuild(ctx, stream);
+            (void)hipEventRecord(b, s);
+            (void)hipEventSynchronize(b);
+            (void)hipEventElapsedTime(&ms, a, b);
+            if (r > 0)
+                t.push_back(ms);
+        }
+        const double med = median(t) * 1e3;
+        std::snprintf(line, sizeof line, "rebuild  map %2dx%d: %9.2f us\n", m[0], m[1], med);
+        rep += line;
+        if (med < best_t) {
+            best_t = med;
+            best.rqd = m[0];
+            best.rqo = m[1];
+        }
+    }
+
+    // 2. streaming frame: mapping x mode
+    best_t = 1e30;
+    const int caps[3] = {0, 256, 1024};
+    for (int fused = 0; fused <= 1 && st == STA_OK; ++fused)
+        for (auto& m : kMaps)
+            for (int ci = 0; ci < (fused ? 3 : 1) && st == STA_OK; ++ci) {
+                sta_set_config(ctx, fused, best.rqd, best.rqo, m[0], m[1], caps[ci]);
+                std::vector<float> t;
+                for (int r = 0; r <= reps && st == STA_OK; ++r) {
+                    float ms = 0.0f;
+                    (void)hipEventRecord(a, s);
+                    st = sta_apply_edits(ctx, ids_dev, states_dev, n_edits, stream);
+                    (void)hipEventRecord(b, s);
+                    if (st == STA_OK)
+                        st = sta_apply_edits(ctx, ids_dev, inv_dev, n_edits, stream);
+                    (void)hipEventSynchronize(b);
+                    (void)hipEventElapsedTime(&ms, a, b);
+                    if (r > 0)
+                        t.push_back(ms);
+                }
+                const double med = median(t) * 1e3;
+                std::snprintf(line, sizeof line, "frame    %s map %2dx%d cap %4d: %9.2f us\n",
+                              fused ? "fused" : "2-launch", m[0], m[1], caps[ci], med);
+                rep += line;
+                if (med < best_t) {
+                    best_t = med;
+                    best.fused = fused;
+                    best.sqd = m[0];
+                    best.sqo = m[1];
+                    best.cap = caps[ci];
+                }
+            }
+    ctx->timing = saved_timing;
+    if (st == STA_OK && hipStreamSynchronize(s) == hipSuccess && sta_status_sync(ctx, stream) == STA_OK) {
+        sta_set_config(ctx, best.fused, best.rqd, best.rqo, best.sqd, best.sqo, best.cap);
+        std::snprintf(line, sizeof line, "chosen: fused %d rebuild %dx%d stream %dx%d cap %d\n", best.fused,
+                      best.rqd, best.rqo, best.sqd, best.sqo, best.cap);
+        rep += line;
+        if (cache)
+            cache_store(cache, key, best);
+    } else {
+        sta_set_config(ctx, saved.fused, saved.rqd, saved.rqo, saved.sqd, saved.sqo, saved.cap);
+        if (st == STA_OK)
+            st = STA_EHIP;
+    }
+    cleanup();
+    return finish(st);
+}
+
+}  // extern "C"

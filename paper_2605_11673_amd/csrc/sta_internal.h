@@ -17,6 +17,7 @@ enum : int32_t {
     ERR_RANGE = 1,       // edit id out of range or state not in {0, 1}
     ERR_DUP = 2,         // the same tet twice in one edit list
     ERR_DEGENERATE = 4,  // det == 0 in an element
+    ERR_TIMEOUT = 8,     // a fused frame's grid barrier gave up (grid not co-resident)
 };
 
 // Control words kept in device memory so that a frame never needs the host
@@ -25,7 +26,15 @@ struct Ctl {
     int32_t err;         // sticky error bits, cleared by sta_status_sync
     int32_t frame_err;   // error bits of the last frame (written by the reduce phase)
     int32_t last_n;      // edit count of the last frame (statistics; also right under graph replay)
-    int32_t pad;
+    uint32_t bar_count;  // grid barrier of the fused frame kernel: arrivals
+    uint32_t bar_gen;    // and generation
+    int32_t pad[2];
+};
+
+// Slot mapping: lanes per block value for diagonal / off-diagonal blocks
+// (1 thread-, 4 quad-, 16 wave-sixteenth-per-slot; diagonal 1/4/16, off 1/4).
+struct MapConfig {
+    int qd = 1, qo = 1;
 };
 
 // Material constants, evaluated once on the host in the fixed order.
@@ -111,12 +120,19 @@ struct sta_ctx {
     int32_t* rowptr = nullptr;  // device
     int32_t* colidx = nullptr;  // device
     std::vector<void*> owned;   // every device allocation
+    // execution configuration (sta_set_config / sta_autotune)
+    sta::MapConfig rebuild_map, stream_map;
+    int fused = 0;          // 1: one persistent launch per frame
+    int frame_grid_cap = 0; // 0: occupancy limit only
+    int frame_max_grid = 0; // co-resident workgroups for the fused kernel (per stream_map)
     // lazily allocated workspaces
     double* cg_ws = nullptr;        // 6 vectors of n_rows + partials
     int32_t* cg_dpos = nullptr;
     sta::CgScalars* cg_s = nullptr;
     sta::CgScalars* cg_host = nullptr;  // pinned
     double* adj_xbar = nullptr;     // 3 doubles per diagonal incidence
+    // batch layout: per mesh node / tet / value offsets (k+1 entries)
+    std::vector<int64_t> node_off, tet_off, nnz_off;
     std::string errmsg;
     // per-kernel event timing
     bool timing = false;
@@ -132,13 +148,18 @@ namespace sta {
 
 // Kernel launchers (assembly.hip).
 hipError_t launch_element(const DevView& v, hipStream_t s);
-hipError_t launch_reduce_all(const DevView& v, hipStream_t s);
+hipError_t launch_reduce_all(const DevView& v, const MapConfig& m, hipStream_t s);
 // Streaming phases.  n_dev (device int32, may be NULL) overrides n_host, which
 // then only sizes the grid (an upper bound on the edit count).
 hipError_t launch_edit_phase(const DevView& v, const int32_t* ids, const uint8_t* states, int32_t n_host,
                              const int32_t* n_dev, hipStream_t s);
-hipError_t launch_touched_phase(const DevView& v, const int32_t* ids, int32_t n_host, const int32_t* n_dev,
-                                hipStream_t s);
+hipError_t launch_touched_phase(const DevView& v, const MapConfig& m, const int32_t* ids, int32_t n_host,
+                                const int32_t* n_dev, hipStream_t s);
+// Fused frame: both phases in one persistent launch of `grid` co-resident workgroups.
+hipError_t frame_max_grid(const MapConfig& m, int device, int* max_grid);
+int frame_grid_for(const MapConfig& m, int32_t n_host, int max_grid, int grid_cap);
+hipError_t launch_frame(const DevView& v, const MapConfig& m, int grid, const int32_t* ids, const uint8_t* states,
+                        int32_t n_host, const int32_t* n_dev, hipStream_t s);
 hipError_t launch_set_params(const DevView& v, const double* x_aos, const double* E, double* xs, double* ys,
                              double* zs, double* Eout, hipStream_t s);
 
@@ -152,6 +173,12 @@ int cg_partials(int n);
 hipError_t launch_cg_init(const CgView& c, const double* b, double rtol, hipStream_t s);
 hipError_t launch_cg_iterations(const CgView& c, int count, int max_iter, hipStream_t s);
 hipError_t launch_cg_output(const CgView& c, double* x, hipStream_t s);
+
+// Context construction shared by single and batched builds (api.hip).
+sta_status build_context(const double* x, int64_t n_nodes, const int32_t* tets, int64_t n_tets, const double* E,
+                         double nu, double rho, double dt, const uint8_t* mask0, void* stream,
+                         const std::vector<int64_t>& node_off, const std::vector<int64_t>& tet_off, sta_ctx** out);
+std::string& build_error();
 
 // Host pattern builder (pattern.cpp).  Fills host arrays; returns "" or an error message.
 struct HostPattern {

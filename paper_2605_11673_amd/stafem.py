@@ -21,9 +21,10 @@ LIB_PATH = os.path.join(HERE, "libstafem.so")
 
 STATUS = {
     0: "STA_OK", -1: "STA_EINVAL", -2: "STA_ENOMEM", -3: "STA_EHIP", -4: "STA_EDEGENERATE",
-    -5: "STA_ESTALE", -6: "STA_ERANGE", -7: "STA_EDUP",
+    -5: "STA_ESTALE", -6: "STA_ERANGE", -7: "STA_EDUP", -8: "STA_ETIMEOUT",
 }
 STA_OK, STA_EINVAL, STA_ENOMEM, STA_EHIP, STA_EDEGENERATE, STA_ESTALE, STA_ERANGE, STA_EDUP = 0, -1, -2, -3, -4, -5, -6, -7
+STA_ETIMEOUT = -8
 
 
 class StafemError(RuntimeError):
@@ -56,6 +57,11 @@ SIGNATURES = {
     "sta_adjoint": (_int, [_vp, _vp, _vp, _vp, _vp]),
     "sta_slot_outer": (_int, [_vp, _vp, _vp, _dbl, _vp, _vp]),
     "sta_cg_solve": (_int, [_vp, _vp, _vp, _vp, _dbl, _int, _vp, ctypes.POINTER(_int), ctypes.POINTER(_dbl)]),
+    "sta_set_config": (_int, [_vp, _int, _int, _int, _int, _int, _int]),
+    "sta_get_config": (_int, [_vp, ctypes.POINTER(_int)]),
+    "sta_autotune": (_int, [_vp, _vp, _vp, _i64, _int, _vp, ctypes.c_char_p, _i64]),
+    "sta_batch_build": (_int, [_int, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _dbl, _vp, _vp, ctypes.POINTER(_vp)]),
+    "sta_batch_offsets": (_int, [_vp, ctypes.POINTER(_int), _vp, _vp, _vp, _vp, _i64]),
     "sta_status_sync": (_int, [_vp, _vp]),
     "sta_last_error": (ctypes.c_char_p, [_vp]),
     "sta_destroy": (None, [_vp]),
@@ -203,7 +209,7 @@ class Assembler:
         d["touched_incidences"] = d["diag_incidences"] + d["off_incidences"]
         return d
 
-    KERNELS = ("element", "reduce", "edits", "touched", "adjoint", "solve", "batch", "spare")
+    KERNELS = ("element", "reduce", "edits", "touched", "adjoint", "solve", "frame", "spare")
 
     def enable_kernel_timing(self, on: bool = True):
         _check(load().sta_enable_kernel_timing(self._ctx, 1 if on else 0), self._ctx)
@@ -255,6 +261,33 @@ class Assembler:
                                    ctypes.byref(it), ctypes.byref(rr)), self._ctx)
         return x, it.value, rr.value
 
+    CONFIG = ("fused", "rebuild_qd", "rebuild_qo", "stream_qd", "stream_qo", "grid_cap")
+
+    def set_config(self, fused=0, rebuild_qd=1, rebuild_qo=1, stream_qd=1, stream_qo=1, grid_cap=0):
+        _check(load().sta_set_config(self._ctx, int(fused), int(rebuild_qd), int(rebuild_qo), int(stream_qd),
+                                     int(stream_qo), int(grid_cap)), self._ctx)
+
+    def get_config(self) -> dict:
+        out = (ctypes.c_int * 6)()
+        _check(load().sta_get_config(self._ctx, out), self._ctx)
+        return dict(zip(self.CONFIG, list(out)))
+
+    def autotune(self, ids: torch.Tensor, states: torch.Tensor, reps: int = 7, stream=None) -> str:
+        """Pick slot mappings and frame mode by timing (see sta_autotune); returns the report."""
+        buf = ctypes.create_string_buffer(8192)
+        _check(load().sta_autotune(self._ctx, _dev_ptr(ids), _dev_ptr(states), int(ids.numel()), int(reps),
+                                   _stream_handle(stream), buf, len(buf)), self._ctx)
+        return buf.value.decode()
+
+    def offsets(self) -> dict:
+        """Per-mesh node / tet / row / value offsets (k+1 entries each)."""
+        k = ctypes.c_int(0)
+        _check(load().sta_batch_offsets(self._ctx, ctypes.byref(k), None, None, None, None, 0), self._ctx)
+        arrs = [np.zeros(k.value + 1, dtype=np.int64) for _ in range(4)]
+        _check(load().sta_batch_offsets(self._ctx, ctypes.byref(k), *[a.ctypes.data for a in arrs], k.value + 1),
+               self._ctx)
+        return dict(zip(("node", "tet", "row", "nnz"), arrs))
+
     def status_sync(self, stream=None) -> int:
         """Synchronise and return (and clear) the first device-detected error code."""
         return int(load().sta_status_sync(self._ctx, _stream_handle(stream)))
@@ -262,6 +295,48 @@ class Assembler:
     def last_error(self) -> str:
         m = load().sta_last_error(self._ctx)
         return m.decode() if m else ""
+
+
+class Batch(Assembler):
+    """Many independent meshes as one context (their disjoint union).
+
+    Mesh j's tet t is global tet ``tet_off[j] + t``; its CSR rows and values
+    are the contiguous ranges given by ``offsets()``.  A frame over all meshes
+    is one apply_edits / apply_edits_dev call with global ids.
+    """
+
+    def __init__(self, meshes, nu, rho, dt, stream=None):
+        """meshes: sequence of (x (n,3), tets (m,4), E (m,), mask0 (m,)) host arrays."""
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the HIP assembly path needs an MI355X")
+        L = load()
+        k = len(meshes)
+        keep = []
+        xs, ts, Es, ms = (ctypes.c_void_p * k)(), (ctypes.c_void_p * k)(), (ctypes.c_void_p * k)(), (ctypes.c_void_p * k)()
+        nn, nt = (ctypes.c_int64 * k)(), (ctypes.c_int64 * k)()
+        for j, (x, t, E, m) in enumerate(meshes):
+            x = np.ascontiguousarray(x, dtype=np.float64)
+            t = np.ascontiguousarray(t, dtype=np.int32)
+            E = np.ascontiguousarray(E, dtype=np.float64)
+            m = np.ascontiguousarray(m, dtype=np.uint8)
+            keep += [x, t, E, m]
+            xs[j], ts[j], Es[j], ms[j] = x.ctypes.data, t.ctypes.data, E.ctypes.data, m.ctypes.data
+            nn[j], nt[j] = x.shape[0], t.shape[0]
+        ctx = _vp()
+        _check(L.sta_batch_build(k, xs, nn, ts, nt, Es, float(nu), float(rho), float(dt), ms, _stream_handle(stream),
+                                 ctypes.byref(ctx)), None)
+        self._ctx = ctx
+        self.nu, self.rho, self.dt = float(nu), float(rho), float(dt)
+        self.n_nodes, self.n_tets = int(sum(nn)), int(sum(nt))
+        r, z, d, o = _i64(), _i64(), _i64(), _i64()
+        _check(L.sta_sizes(ctx, ctypes.byref(r), ctypes.byref(z), ctypes.byref(d), ctypes.byref(o)), ctx)
+        self.n_rows, self.nnz, self.n_diag_blocks, self.n_off_blocks = r.value, z.value, d.value, o.value
+        self.k = k
+
+    @classmethod
+    def from_workloads(cls, ws, stream=None):
+        w0 = ws[0]
+        return cls([(w.x, w.tets, w.E, w.mask0) for w in ws], w0.nu, w0.rho, w0.dt, stream)
 
 
 def upload_frame(ids: np.ndarray, states: np.ndarray, device="cuda"):

@@ -1,0 +1,171 @@
+"""Slot mappings, the fused one-launch frame, batched meshes and the autotuner.
+
+Every mapping (lanes per block value: 1, 4 or 16 for diagonal blocks, 1 or 4
+for off-diagonal ones) and both frame modes add the same terms in the same
+order, so all of them must reproduce the oracle bit for bit.  A batch is the
+disjoint union of its meshes: each mesh's slice of the values must equal the
+oracle of that mesh alone at every checked frame.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2605_11673_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+MAPS = [(1, 1), (1, 4), (4, 1), (4, 4), (16, 1), (16, 4)]
+
+
+def S():
+    from paper_2605_11673_amd import stafem
+    return stafem
+
+
+def bits(a):
+    return np.ascontiguousarray(a, dtype=np.float64).view(np.uint64)
+
+
+def host_values(asm):
+    v = asm.values()
+    torch.cuda.synchronize()
+    return v.cpu().numpy()
+
+
+def check(got, want, what):
+    if not np.array_equal(bits(got), bits(want)):
+        bad = np.nonzero(bits(got) != bits(want))[0]
+        raise AssertionError(f"{what}: {len(bad)} values differ, first at {bad[0]}")
+
+
+@pytest.mark.parametrize("fused", [0, 1])
+@pytest.mark.parametrize("qd,qo", MAPS)
+def test_mappings_and_modes_bitwise(qd, qo, fused):
+    """Refinement superset (diagonal segments up to 48 terms: several load chunks) and a
+    fracture mesh; rebuild and streaming with the given mapping / mode, every frame."""
+    Sm = S()
+    for w in (W.make_refinement(seed=1, n=6, frames=6), W.make_fracture(seed=1, n=10, counts=[200, 900, 40])):
+        frames = list(w.frames) + ([] if "refine" in w.name else W.merge_stream(w.frames))
+        pat = oracle.pattern(w.n_nodes, w.tets)
+        asm = Sm.Assembler.from_workload(w)
+        asm.set_config(fused=fused, rebuild_qd=qd, rebuild_qo=qo, stream_qd=qd, stream_qo=qo)
+        asm.full_rebuild()
+        check(host_values(asm), oracle.rebuild_workload(w, w.mask0, pat), f"{w.name} rebuild {qd}x{qo}")
+        mask = w.mask0.copy()
+        for t, (ids, st) in enumerate(frames):
+            asm.apply_edits(*Sm.upload_frame(ids, st))
+            mask[ids] = st
+            check(host_values(asm), oracle.rebuild_workload(w, mask, pat),
+                  f"{w.name} frame {t} map {qd}x{qo} fused {fused}")
+        assert asm.status_sync() == Sm.STA_OK
+        asm.close()
+
+
+def test_fused_frame_errors_roll_back():
+    Sm = S()
+    w = W.make_cube(5)
+    asm = Sm.Assembler.from_workload(w)
+    asm.set_config(fused=1, stream_qd=4)
+    v0 = host_values(asm)
+    asm.apply_edits(*Sm.upload_frame(np.array([3, 9, 3], np.int32), np.zeros(3, np.uint8)))
+    assert asm.status_sync() == Sm.STA_EDUP
+    check(host_values(asm), v0, "fused duplicate rollback")
+    asm.apply_edits(*Sm.upload_frame(np.array([3, 999], np.int32), np.zeros(2, np.uint8)))
+    assert asm.status_sync() == Sm.STA_ERANGE
+    check(host_values(asm), v0, "fused range rollback")
+    asm.close()
+
+
+def batch_frames(ws, tet_off, t):
+    ids = [w.frames[t][0].astype(np.int64) + tet_off[j] for j, w in enumerate(ws)]
+    st = [w.frames[t][1] for w in ws]
+    return np.concatenate(ids).astype(np.int32), np.concatenate(st).astype(np.uint8)
+
+
+def run_batch(ws, check_frames, fused, qd, label):
+    """One graph (sta_apply_edits_dev captured once) replayed per frame; each mesh's
+    slice vs the oracle of that mesh at the checked frames."""
+    Sm = S()
+    print(f"[batch] {label}: {len(ws)} meshes, {sum(w.n_tets for w in ws)} tets", flush=True)
+    b = Sm.Batch.from_workloads(ws)
+    b.set_config(fused=fused, stream_qd=qd)
+    off = b.offsets()
+    pats = [oracle.pattern(w.n_nodes, w.tets) for w in ws]
+    for j, w in enumerate(ws):  # each mesh's slice of the pattern is its own pattern
+        rp, ci = b.pattern()
+        r0, r1 = off["row"][j], off["row"][j + 1]
+        assert np.array_equal(rp[r0:r1 + 1] - rp[r0], pats[j][0])
+        assert np.array_equal(ci[rp[r0]:rp[r1]] - 3 * off["node"][j], pats[j][1])
+    cap = max(len(batch_frames(ws, off["tet"], t)[0]) for t in range(len(ws[0].frames)))
+    ids = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    st = torch.zeros(cap, dtype=torch.uint8, device="cuda")
+    n = torch.zeros(1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.apply_edits_dev(ids, st, n)
+    masks = [w.mask0.copy() for w in ws]
+    for t in range(len(ws[0].frames)):
+        gi, gs = batch_frames(ws, off["tet"], t)
+        ids[:len(gi)].copy_(torch.from_numpy(gi))
+        st[:len(gi)].copy_(torch.from_numpy(gs))
+        n.fill_(len(gi))
+        g.replay()
+        torch.cuda.synchronize()
+        for j, w in enumerate(ws):
+            masks[j][w.frames[t][0]] = w.frames[t][1]
+        if t in check_frames:
+            vals = host_values(b)
+            for j, w in enumerate(ws):
+                want = oracle.rebuild(w.x, w.tets, w.E, w.nu, w.rho, w.dt, masks[j], *pats[j])
+                check(vals[off["nnz"][j]:off["nnz"][j + 1]], want, f"{label} frame {t} mesh {j}")
+    assert b.status_sync() == Sm.STA_OK
+    return b, masks
+
+
+@pytest.mark.parametrize("fused", [0, 1])
+def test_batch_small_every_frame(fused):
+    ws = W.make_batch(seed=2, count=10, sizes=[2, 5, 3, 7, 1, 4, 6, 2, 8, 3])
+    b, _ = run_batch(ws, set(range(24)), fused, 4, f"small batch fused={fused}")
+    b.close()
+
+
+def test_batch_full_size():
+    """64 meshes of 6n^3 tets, n log-uniform (1k..120k tets each, ~1.4M tets in all), each
+    with its own 24-frame fracture stream; one fused launch per frame from one captured
+    graph; every mesh bitwise vs the oracle at frames 0, 6, 12, 18, 23, and the batch's
+    values at the end bitwise equal to each mesh run alone."""
+    Sm = S()
+    ws = W.make_batch(seed=0)
+    b, masks = run_batch(ws, {0, 6, 12, 18, 23}, 1, 1, "batch 64")
+    vals = host_values(b)
+    off = b.offsets()
+    for j in (0, 17, 40, 63):
+        a = Sm.Assembler.from_workload(ws[j])
+        for ids, st in ws[j].frames:
+            a.apply_edits(*Sm.upload_frame(ids, st))
+        check(vals[off["nnz"][j]:off["nnz"][j + 1]], host_values(a), f"batch vs single mesh {j}")
+        a.close()
+    b.close()
+
+
+def test_autotune_and_cache(tmp_path, monkeypatch):
+    Sm = S()
+    monkeypatch.setenv("STA_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    w = W.make_fracture(seed=3, n=12, counts=[300, 50])
+    pat = oracle.pattern(w.n_nodes, w.tets)
+    asm = Sm.Assembler.from_workload(w)
+    di, ds = Sm.upload_frame(*w.frames[0])
+    rep = asm.autotune(di, ds, reps=3)
+    assert "chosen" in rep, rep
+    cfg = asm.get_config()
+    check(host_values(asm), oracle.rebuild_workload(w, w.mask0, pat), "after tuning (state restored)")
+    for t, (ids, st) in enumerate(w.frames):
+        asm.apply_edits(*Sm.upload_frame(ids, st))
+        check(host_values(asm), oracle.rebuild_workload(w, w.mask_after(t), pat), f"tuned frame {t}")
+    asm.close()
+    asm2 = Sm.Assembler.from_workload(w)
+    rep2 = asm2.autotune(di, ds)
+    assert rep2.startswith("cached") and asm2.get_config() == cfg
+    asm2.close()
