@@ -247,16 +247,21 @@ class Stream:
         return m
 
     def per_frame(self, reps):
-        """Per-frame latency: one host-launched sta_apply_edits between two HIP events on
-        the launch stream, warm and after writing 1 GiB to evict the caches; the full
-        rebuild at the same mask; medians."""
+        """Per-frame latency: one sta_apply_edits between two HIP events on the launch
+        stream, warm and after writing 1 GiB to evict the caches; the full rebuild at
+        the same mask; medians."""
         torch, asm = self.torch, self.asm
         flush = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")  # > 256 MB infinity cache
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
 
         def timed(fn, cold):
+            # queue the events and the launches behind GPU work (the cache flush, or
+            # a spin that touches no memory), so that the interval is GPU time alone
+            # and not the host's launch latency
             if cold:
                 flush.fill_(1)
+            else:
+                torch.cuda._sleep(200000)
             ev[0].record()
             fn()
             ev[1].record()
@@ -363,7 +368,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the refinement and batch workloads")
     ap.add_argument("--no-tune", action="store_true", help="keep the default configuration")
     ap.add_argument("--config", default=None,
-                    help="force fused,rebuild_qd,rebuild_qo,stream_qd,stream_qo,grid_cap (skips tuning)")
+                    help="force fused,rebuild_qd,rebuild_qo,stream_qd,stream_qo,grid_cap,rebuild_nt (skips tuning)")
     ap.add_argument("--cpu-sample", type=int, default=12, help="oracle rebuilds in the CPU baseline sample")
     ap.add_argument("--quick", action="store_true",
                     help="headline timed steps, 3 rebuilds and a 256 MiB reference copy only (for profiler runs)")
@@ -428,6 +433,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if not args.quick:
+        out["latency_floor"] = stafem.latency_probe()
         out["roofline_rebuild"] = s.rebuild_roofline()
         out.update(s.per_frame(args.reps))
         out["stream_vs_rebuild"]["pipelined_ratio"] = round(

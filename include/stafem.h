@@ -209,10 +209,12 @@ sta_status sta_cg_solve(sta_ctx* ctx, const double* values_dev, const double* b_
  *               the same order: results are bit-identical.
  *   grid_cap    upper bound on the fused kernel's workgroups (0 = the
  *               co-resident limit).
- * sta_get_config writes the same 6 integers.  Defaults: 0, 1, 1, 1, 1, 0. */
+ *   rebuild_nt  1: the rebuild streams contributions and values with
+ *               non-temporal cache hints (each byte is touched once).
+ * sta_get_config writes the same 7 integers.  Defaults: 0, 1, 1, 1, 1, 0, 0. */
 sta_status sta_set_config(sta_ctx* ctx, int fused, int rebuild_qd, int rebuild_qo, int stream_qd, int stream_qo,
-                          int grid_cap);
-sta_status sta_get_config(const sta_ctx* ctx, int* out6);
+                          int grid_cap, int rebuild_nt);
+sta_status sta_get_config(const sta_ctx* ctx, int* out7);
 
 /* Autotuner: times every slot mapping for the full rebuild, and every
  * mapping x {two launches, fused with grid caps} for one streaming frame
@@ -240,6 +242,15 @@ sta_status sta_batch_build(int k, const double* const* x, const int64_t* n_nodes
  * sta_build_pattern is a batch of one. */
 sta_status sta_batch_offsets(const sta_ctx* ctx, int* k, int64_t* node_off, int64_t* tet_off, int64_t* row_off,
                              int64_t* nnz_off, int64_t capacity);
+
+/* Latency floor of this GPU (no context needed; allocates ~257 MB
+ * temporarily; synchronises `stream`): out4[0] = microseconds per empty
+ * kernel launched back to back on one stream, out4[1] = nanoseconds per
+ * dependent global load over a 256 MB working set, out4[2] = the same over
+ * an L2-resident 1 MB set, out4[3] = nanoseconds per dependent returning
+ * device-scope atomic.  A streaming frame is two launches with a few
+ * dependent round trips each, so these numbers bound its latency. */
+sta_status sta_latency_probe(void* stream, double* out4);
 
 /* Synchronise `stream`, return and clear the first error the device
  * recorded (STA_ERANGE, STA_EDUP, STA_EDEGENERATE), else STA_OK. */

@@ -273,7 +273,7 @@ sta_status build_context(const double* x, int64_t n_nodes, const int32_t* tets, 
     v.wg_err = wg_err;
     v.ctl = ctl;
 
-    if (e == hipSuccess) e = launch_element(v, s);
+    if (e == hipSuccess) e = launch_element(v, false, s);
     if (e == hipSuccess) e = launch_reduce_all(v, c->rebuild_map, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     int32_t bits = 0;
@@ -351,7 +351,7 @@ sta_status sta_full_rebuild(sta_ctx* ctx, void* stream)
     if (!ctx)
         return STA_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = timed(ctx, STA_KERNEL_ELEMENT, s, [&] { return launch_element(ctx->v, s); });
+    hipError_t e = timed(ctx, STA_KERNEL_ELEMENT, s, [&] { return launch_element(ctx->v, ctx->rebuild_map.nt != 0, s); });
     if (e == hipSuccess)
         e = timed(ctx, STA_KERNEL_REDUCE, s, [&] { return launch_reduce_all(ctx->v, ctx->rebuild_map, s); });
     if (e != hipSuccess)
@@ -572,30 +572,32 @@ sta_status sta_status_sync(sta_ctx* ctx, void* stream)
 }
 
 sta_status sta_set_config(sta_ctx* ctx, int fused, int rebuild_qd, int rebuild_qo, int stream_qd, int stream_qo,
-                          int grid_cap)
+                          int grid_cap, int rebuild_nt)
 {
     if (!ctx || (fused != 0 && fused != 1) || !valid_map(rebuild_qd, rebuild_qo) || !valid_map(stream_qd, stream_qo) ||
-        grid_cap < 0)
+        grid_cap < 0 || (rebuild_nt != 0 && rebuild_nt != 1))
         return STA_EINVAL;
     if (stream_qd != ctx->stream_map.qd || stream_qo != ctx->stream_map.qo)
         ctx->frame_max_grid = 0;
     ctx->fused = fused;
-    ctx->rebuild_map = MapConfig{rebuild_qd, rebuild_qo};
-    ctx->stream_map = MapConfig{stream_qd, stream_qo};
+    ctx->rebuild_map = MapConfig{rebuild_qd, rebuild_qo, rebuild_nt};
+    ctx->stream_map = MapConfig{stream_qd, stream_qo, 0};
     ctx->frame_grid_cap = grid_cap;
     return STA_OK;
 }
 
-sta_status sta_get_config(const sta_ctx* ctx, int* out6)
+sta_status sta_get_config(const sta_ctx* ctx, int* out7)
 {
-    if (!ctx || !out6)
+    if (!ctx || !out7)
         return STA_EINVAL;
+    int* out6 = out7;
     out6[0] = ctx->fused;
     out6[1] = ctx->rebuild_map.qd;
     out6[2] = ctx->rebuild_map.qo;
     out6[3] = ctx->stream_map.qd;
     out6[4] = ctx->stream_map.qo;
     out6[5] = ctx->frame_grid_cap;
+    out6[6] = ctx->rebuild_map.nt;
     return STA_OK;
 }
 

@@ -31,6 +31,35 @@ constexpr int kBlock = 256;
 constexpr int kXcds = 8;
 constexpr int kEditLanes = 16;     // phase 1: one lane per block slot (10 used), power of two
 
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+// Loads and stores with an optional non-temporal (streaming) cache hint, for
+// data touched exactly once per launch (the rebuild's contributions and values).
+template <bool NT>
+__device__ __forceinline__ double ld(const double* p)
+{
+    if (NT)
+        return __builtin_nontemporal_load(p);
+    return *p;
+}
+template <bool NT>
+__device__ __forceinline__ void st(double* p, double x)
+{
+    if (NT)
+        __builtin_nontemporal_store(x, p);
+    else
+        *p = x;
+}
+template <bool NT>
+__device__ __forceinline__ void st2(double* p, double a, double b)
+{
+    const dvec2 x = {a, b};
+    if (NT)
+        __builtin_nontemporal_store(x, reinterpret_cast<dvec2*>(p));
+    else
+        *reinterpret_cast<dvec2*>(p) = x;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs.  Remap so that each
 // XCD walks one contiguous range of the work: neighbouring blocks share
 // contribution, descriptor and CSR cache lines, and each XCD has its own L2.
@@ -54,17 +83,10 @@ __device__ __forceinline__ void cross3(const double* a, const double* b, double*
     c[2] = (a[0] * b[1]) - (a[1] * b[0]);
 }
 
-// Basis gradients, scaled moduli and lumped mass of tet e, in the fixed order.
-__device__ __forceinline__ void element_geometry(const DevView& v, int e, int4 t, Geo& G)
+// Basis gradients, scaled moduli and lumped mass of a tet from its vertex
+// coordinates X and Young's modulus E, in the fixed order.
+__device__ __forceinline__ void geometry_from(const DevView& v, const double (&X)[4][3], double E, Geo& G)
 {
-    const int id[4] = {t.x, t.y, t.z, t.w};
-    double X[4][3];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        X[a][0] = v.xs[id[a]];
-        X[a][1] = v.ys[id[a]];
-        X[a][2] = v.zs[id[a]];
-    }
     double d[4][3];
 #pragma unroll
     for (int k = 1; k <= 3; ++k)
@@ -86,13 +108,30 @@ __device__ __forceinline__ void element_geometry(const DevView& v, int e, int4 t
     for (int i = 0; i < 3; ++i)
         G.g[0][i] = -((G.g[1][i] + G.g[2][i]) + G.g[3][i]);
     const double V = fabs(det) / 6.0;
-    const double E = v.E[e];
     const double lam = E * v.mat.clam;
     const double mu = E * v.mat.cmu;
     G.lamV = (lam * V) * v.mat.cdt;
     G.muV = (mu * V) * v.mat.cdt;
     G.ml = (v.mat.rho * V) * 0.25;
     G.det = det;
+}
+
+__device__ __forceinline__ void load_vertices(const DevView& v, int4 t, double (&X)[4][3])
+{
+    const int id[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        X[a][0] = v.xs[id[a]];
+        X[a][1] = v.ys[id[a]];
+        X[a][2] = v.zs[id[a]];
+    }
+}
+
+__device__ __forceinline__ void element_geometry(const DevView& v, int e, int4 t, Geo& G)
+{
+    double X[4][3];
+    load_vertices(v, t, X);
+    geometry_from(v, X, v.E[e], G);
 }
 
 __device__ __forceinline__ double dot3(const double* a, const double* b)
@@ -119,6 +158,7 @@ constexpr int PB[6] = {1, 2, 3, 2, 3, 3};
 // Compute tet e's element matrix and store its 78 distinct values at the
 // tet's 10 incidence positions.  Off-diagonal blocks are stored in block
 // orientation (row node = smaller node id).  pos: the tet's 10 positions.
+template <bool NT = false>
 __device__ __forceinline__ void store_element(const DevView& v, int e, int4 t, const int* pos)
 {
     Geo G;
@@ -129,10 +169,10 @@ __device__ __forceinline__ void store_element(const DevView& v, int e, int4 t, c
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
         const double s = dot3(G.g[a], G.g[a]);
-        double2* dst = reinterpret_cast<double2*>(v.cd + 6 * (size_t)pos[a]);
-        dst[0] = make_double2(entry(G.g[a], G.g[a], s, G, 0, 0, true), entry(G.g[a], G.g[a], s, G, 0, 1, true));
-        dst[1] = make_double2(entry(G.g[a], G.g[a], s, G, 0, 2, true), entry(G.g[a], G.g[a], s, G, 1, 1, true));
-        dst[2] = make_double2(entry(G.g[a], G.g[a], s, G, 1, 2, true), entry(G.g[a], G.g[a], s, G, 2, 2, true));
+        double* dst = v.cd + 6 * (size_t)pos[a];
+        st2<NT>(dst + 0, entry(G.g[a], G.g[a], s, G, 0, 0, true), entry(G.g[a], G.g[a], s, G, 0, 1, true));
+        st2<NT>(dst + 2, entry(G.g[a], G.g[a], s, G, 0, 2, true), entry(G.g[a], G.g[a], s, G, 1, 1, true));
+        st2<NT>(dst + 4, entry(G.g[a], G.g[a], s, G, 1, 2, true), entry(G.g[a], G.g[a], s, G, 2, 2, true));
     }
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
@@ -149,27 +189,27 @@ __device__ __forceinline__ void store_element(const DevView& v, int e, int4 t, c
         for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int j = 0; j < 3; ++j)
-                dst[3 * i + j] = entry(ga, gb, s, G, i, j, false);
+                st<NT>(dst + 3 * i + j, entry(ga, gb, s, G, i, j, false));
     }
 }
 
 // Zero the 78 slots of an inactive tet.
+template <bool NT = false>
 __device__ __forceinline__ void zero_element(const DevView& v, const int* pos)
 {
-    const double2 z = make_double2(0.0, 0.0);
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        double2* dst = reinterpret_cast<double2*>(v.cd + 6 * (size_t)pos[a]);
-        dst[0] = z;
-        dst[1] = z;
-        dst[2] = z;
+        double* dst = v.cd + 6 * (size_t)pos[a];
+        st2<NT>(dst + 0, 0.0, 0.0);
+        st2<NT>(dst + 2, 0.0, 0.0);
+        st2<NT>(dst + 4, 0.0, 0.0);
     }
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         double* dst = v.co + 9 * (size_t)pos[4 + q];
 #pragma unroll
         for (int j = 0; j < 9; ++j)
-            dst[j] = 0.0;
+            st<NT>(dst + j, 0.0);
     }
 }
 
@@ -181,7 +221,7 @@ __device__ __forceinline__ void zero_element(const DevView& v, const int* pos)
 // lane that holds it.  The additions are the same whatever Q is, so the
 // result is bit-identical across mappings.  src0: wave lane of the group's
 // lane 0; groups of Q lanes never straddle a wave.
-template <int Q, int CH>
+template <int Q, int CH, bool NT = false>
 __device__ __forceinline__ double seg_sum(const double* __restrict__ c, int stride, int vi, int k0, int k1, int q,
                                           int src0)
 {
@@ -191,7 +231,7 @@ __device__ __forceinline__ double seg_sum(const double* __restrict__ c, int stri
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             const int k = base + q + j * Q;
-            t[j] = k < k1 ? c[(size_t)k * stride + vi] : 0.0;
+            t[j] = k < k1 ? ld<NT>(c + (size_t)k * stride + vi) : 0.0;
         }
         if (Q == 1) {
 #pragma unroll
@@ -224,23 +264,23 @@ __device__ __constant__ int kDiagQ[6] = {0, 1, 2, 1, 2, 2};
 // Recompute value vi (0..5 unique diagonal values, 0..8 off-diagonal) of the
 // block described by d and write it (and its mirror) into the CSR values.
 // All QD (or QO) lanes of the group call this; lane q == 0 writes.
-template <int QD, int QO>
+template <int QD, int QO, bool NT = false>
 __device__ __forceinline__ void block_value(const DevView& v, const BlockDesc& d, int vi, int q, int src0)
 {
     if (d.kind == 0) {
-        const double acc = seg_sum<QD, DiagChunk<QD>::CH>(v.cd, 6, vi, d.k0, d.k1, q, src0);
+        const double acc = seg_sum<QD, DiagChunk<QD>::CH, NT>(v.cd, 6, vi, d.k0, d.k1, q, src0);
         if (q == 0) {
             const int p = kDiagP[vi], r = kDiagQ[vi];
-            v.values[d.up + p * d.rl + r] = acc;
+            st<NT>(v.values + d.up + p * d.rl + r, acc);
             if (p != r)
-                v.values[d.up + r * d.rl + p] = acc;
+                st<NT>(v.values + d.up + r * d.rl + p, acc);
         }
     } else {
-        const double acc = seg_sum<QO, OffChunk<QO>::CH>(v.co, 9, vi, d.k0, d.k1, q, src0);
+        const double acc = seg_sum<QO, OffChunk<QO>::CH, NT>(v.co, 9, vi, d.k0, d.k1, q, src0);
         if (q == 0) {
             const int p = vi / 3, r = vi - 3 * (vi / 3);
-            v.values[d.up + p * d.rl + r] = acc;
-            v.values[d.lo + r * d.rlj + p] = acc;
+            st<NT>(v.values + d.up + p * d.rl + r, acc);
+            st<NT>(v.values + d.lo + r * d.rlj + p, acc);
         }
     }
 }
@@ -273,6 +313,7 @@ __device__ __forceinline__ void store_desc(BlockDesc* p, const BlockDesc& d)
 // ---------------------------------------------------------------------------
 
 // Every candidate: active -> element matrix into its slots, inactive -> zeros.
+template <bool NT>
 __global__ __launch_bounds__(kBlock) void k_element(DevView v)
 {
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
@@ -284,14 +325,14 @@ __global__ __launch_bounds__(kBlock) void k_element(DevView v)
     for (int j = 0; j < 10; ++j)
         pos[j] = v.e2p[10 * (size_t)e + j];
     if (v.mask[e])
-        store_element(v, e, v.T[e], pos);
+        store_element<NT>(v, e, v.T[e], pos);
     else
-        zero_element(v, pos);
+        zero_element<NT>(v, pos);
 }
 
 // Lanes: 6*QD per diagonal block (section padded to whole waves), then 9*QO
 // per off-diagonal block.
-template <int QD, int QO>
+template <int QD, int QO, bool NT>
 __global__ __launch_bounds__(kBlock) void k_reduce_all(DevView v, int64_t diag_lanes)
 {
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
@@ -303,7 +344,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_all(DevView v, int64_t diag_l
             return;
         const int rem = (int)(t - (int64_t)b * (6 * QD));
         const int q = rem % QD;
-        block_value<QD, QO>(v, load_desc(v.desc + b), rem / QD, q, lane - q);
+        block_value<QD, QO, NT>(v, load_desc(v.desc + b), rem / QD, q, lane - q);
     } else {
         const int64_t u = t - diag_lanes;
         const int o = (int)(u / (9 * QO));
@@ -311,7 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_all(DevView v, int64_t diag_l
             return;
         const int rem = (int)(u - (int64_t)o * (9 * QO));
         const int q = rem % QO;
-        block_value<QD, QO>(v, load_desc(v.desc + v.nd + o), rem / QO, q, lane - q);
+        block_value<QD, QO, NT>(v, load_desc(v.desc + v.nd + o), rem / QO, q, lane - q);
     }
 }
 
@@ -348,9 +389,10 @@ __device__ __forceinline__ void store_slot_ab(const DevView& v, const Geo& G, co
     }
 }
 
-// Write block slot r (0..3 diagonal a=r, 4..9 pairs 01 02 03 12 13 23) of tet
-// e: its element-matrix values or, for an inactive tet, zeros.
-__device__ __forceinline__ void store_slot(const DevView& v, int e, int4 t, int r, int pos, bool active)
+// Write block slot r (0..3 diagonal a=r, 4..9 pairs 01 02 03 12 13 23) of a
+// tet with vertex ids t: its element-matrix values (geometry G) when active,
+// zeros when not.
+__device__ __forceinline__ void store_slot(const DevView& v, int4 t, const Geo& G, int r, int pos, bool active)
 {
     if (!active) {
         if (r < 4) {
@@ -367,8 +409,6 @@ __device__ __forceinline__ void store_slot(const DevView& v, int e, int4 t, int 
         }
         return;
     }
-    Geo G;
-    element_geometry(v, e, t, G);
     if (G.det == 0.0 && r == 0)
         atomicOr(&v.ctl->err, ERR_DEGENERATE);
     const int id[4] = {t.x, t.y, t.z, t.w};
@@ -385,6 +425,9 @@ __device__ __forceinline__ void store_slot(const DevView& v, int e, int4 t, int 
     default: store_slot_ab<2, 3>(v, G, id, pos); break;
     }
 }
+
+__device__ BlockDesc kNoClaim = {0, 0, 0, 0, 0, 0, -1, -1};
+__device__ int32_t kNoTet = -1;
 
 __device__ __forceinline__ BlockDesc empty_desc()
 {
@@ -405,20 +448,23 @@ __device__ __forceinline__ int frame_count(int32_t n_host, const int32_t* n_dev,
     return n;
 }
 
-// Phase 1 for lane r of edit i (16 lanes per edit; lane r < 10 owns block
-// slot r).  Validate the edit; lane 0 takes the tet's stamp (a second edit of
-// the same tet in this frame finds it taken: duplicate) and reads its mask
-// bit.  If the state changes, each slot lane claims its block (first
+// Phase 1 for lane r of edit i = (tet id, requested state st); 16 lanes per
+// edit, lane r < 10 owns block slot r.  Validate the edit; lane 0 takes the
+// tet's stamp (a second edit of the same tet in this frame finds it taken:
+// duplicate).  If the state changes, each slot lane claims its block (first
 // claimant wins; the claim record carries the block descriptor), the owner
 // flips the mask bit and the slot lanes rewrite the tet's 78 contribution
 // slots (element matrix on activation, zeros on deactivation).  Returns the
 // lane's error bits.  All 16 lanes of the edit must call it together.
-__device__ __forceinline__ int edit_lane(const DevView& v, const int32_t* __restrict__ ids,
-                                         const uint8_t* __restrict__ states, int i, int r)
+//
+// The frame is a short chain of dependent memory round trips, so its time is
+// their latency: every load that needs only the tet id (incidence positions,
+// mask bit, vertex ids, modulus) and then the block descriptors and vertex
+// coordinates are issued before the first atomic or store, which the compiler
+// could not move them across.
+__device__ __forceinline__ int edit_lane(const DevView& v, int id, unsigned st, int i, int r)
 {
     BlockDesc* rec = v.rec + 10 * (size_t)i;
-    const int id = ids[i];
-    const unsigned st = states[i];
     if (id < 0 || id >= v.n_tets || st > 1u) {
         if (r < 10)
             store_desc(rec + r, empty_desc());
@@ -428,26 +474,38 @@ __device__ __forceinline__ int edit_lane(const DevView& v, const int32_t* __rest
         }
         return 0;
     }
-    int eb = 0, ep = 0;
-    if (r < 10) {
-        eb = v.e2b[10 * (size_t)id + r];
+    const bool slot = r < 10;
+    // round trip 1: everything indexed by the tet id, and the tet's stamp
+    uint32_t eb = 0;
+    int ep = 0;
+    if (slot) {
+        eb = (uint32_t)v.e2b[10 * (size_t)id + r];
         ep = v.e2p[10 * (size_t)id + r];
     }
-    const uint8_t prev = v.mask[id];
-    int owner = 1;
-    if (r == 0)
-        owner = atomicExch(&v.estamp[id], 1u) == 0u ? 1 : 0;
-    owner = __shfl(owner, (threadIdx.x & 63) & ~(kEditLanes - 1), 64);
-    const bool change = prev != st;
-    if (r < 10) {
-        BlockDesc d = empty_desc();
-        if (change) {
-            const BlockDesc bd = load_desc(v.desc + eb);
-            if (atomicExch(&v.bstamp[eb], 1u) == 0u)
-                d = bd;
-        }
-        store_desc(rec + r, d);
+    int4 t = make_int4(0, 0, 0, 0);
+    double E = 0.0;
+    if (slot && st) {
+        t = v.T[id];
+        E = v.E[id];
     }
+    const uint8_t prev = v.mask[id];
+    unsigned taken = 0u;
+    if (r == 0)
+        taken = atomicExch(&v.estamp[id], 1u);
+    // round trip 2: block claims, block descriptors, vertex coordinates
+    const bool change = prev != st;
+    unsigned claimed = 1u;
+    if (slot && change)
+        claimed = atomicExch(&v.bstamp[eb], 1u);
+    BlockDesc bd = empty_desc();
+    if (slot)
+        bd = load_desc(v.desc + eb);
+    double X[4][3];
+    if (slot && st)
+        load_vertices(v, t, X);
+    // the atomics' results pass through cross-lane moves, which the compiler
+    // keeps in place, so their waits fall here and after the slot stores
+    const int owner = __shfl(taken, (threadIdx.x & 63) & ~(kEditLanes - 1), 64) == 0u;
     int bits = 0;
     if (!owner) {
         if (r == 0)
@@ -455,9 +513,17 @@ __device__ __forceinline__ int edit_lane(const DevView& v, const int32_t* __rest
     } else if (change) {
         if (r == 0)
             v.mask[id] = (uint8_t)st;
-        if (r < 10)
-            store_slot(v, id, v.T[id], r, ep, st != 0u);
+        if (slot) {
+            Geo G;
+            if (st)
+                geometry_from(v, X, E, G);
+            store_slot(v, t, G, r, ep, st != 0u);
+        }
     }
+    // the claim record is written last, so the claim's round trip overlaps the slot arithmetic
+    claimed = __shfl(claimed, threadIdx.x & 63, 64);
+    if (slot)
+        store_desc(rec + r, claimed == 0u ? bd : empty_desc());
     if (r == 0)
         v.undo[i] = (owner && change) ? prev : (uint8_t)0xFF;
     return bits;
@@ -472,49 +538,54 @@ struct Phase2 {
     static constexpr int kLanes = (24 * QD + 54 * QO + 15) / 16 * 16;
 };
 
-// Phase 2 for lane r of edit i.  fe: the frame's error bits.  Without an
-// error the lane group re-sums its value if the edit claimed the block; with
-// one, lane 0 undoes the edit's mask flip and slot rewrite.  Either way the
-// frame's stamps are cleared for the next frame.
+// Phase 2 lane r of an edit: which claim record (j) and which of its values
+// (vi), and the lane's place q in the value's lane group.  Returns false for
+// the padding lanes past the last off-diagonal value.
 template <int QD, int QO>
-__device__ __forceinline__ void touched_lane(const DevView& v, const int32_t* __restrict__ ids, int fe, int i, int r)
+__device__ __forceinline__ bool touched_slot(int r, int& j, int& vi, int& q)
 {
-    int j, vi, q;
     if (r < Phase2<QD, QO>::kDiag) {
         j = r / (6 * QD);
         const int rem = r - j * (6 * QD);
         vi = rem / QD;
         q = rem - vi * QD;
-    } else {
-        const int rr = r - Phase2<QD, QO>::kDiag;
-        if (rr >= 54 * QO)
-            return;
-        j = 4 + rr / (9 * QO);
-        const int rem = rr - (j - 4) * (9 * QO);
-        vi = rem / QO;
-        q = rem - vi * QO;
+        return true;
     }
-    const BlockDesc d = load_desc(v.rec + 10 * (size_t)i + j);
+    const int rr = r - Phase2<QD, QO>::kDiag;
+    j = 4 + rr / (9 * QO);
+    const int rem = rr - (j - 4) * (9 * QO);
+    vi = rem / QO;
+    q = rem - vi * QO;
+    return rr < 54 * QO;
+}
+
+// Phase 2 for lane r of edit i (tet id), given its claim record d (loaded
+// by the caller before the frame's error bits are known, so that the two
+// round trips overlap).  fe: the frame's error bits.  Without an error the
+// lane group re-sums its value if the edit claimed the block; with one, lane
+// 0 undoes the edit's mask flip and slot rewrite.  Either way the frame's
+// stamps are cleared for the next frame.
+template <int QD, int QO>
+__device__ __forceinline__ void touched_lane(const DevView& v, const BlockDesc& d, int id, int fe, int i, int r,
+                                             int vi, int q)
+{
     if (!fe && d.kind >= 0)
         block_value<QD, QO>(v, d, vi, q, (threadIdx.x & 63) - q);
     if (vi == 0 && q == 0 && d.kind >= 0)
         v.bstamp[d.block] = 0u;
-    if (r == 0) {
-        const int id = ids[i];
-        if (id >= 0 && id < v.n_tets) {
-            v.estamp[id] = 0u;
-            const uint8_t u = v.undo[i];
-            if (fe && u != 0xFF) {
-                int ep[10];
+    if (r == 0 && id >= 0 && id < v.n_tets) {
+        v.estamp[id] = 0u;
+        const uint8_t u = v.undo[i];
+        if (fe && u != 0xFF) {
+            int ep[10];
 #pragma unroll
-                for (int k = 0; k < 10; ++k)
-                    ep[k] = v.e2p[10 * (size_t)id + k];
-                v.mask[id] = u;
-                if (u)
-                    store_element(v, id, v.T[id], ep);
-                else
-                    zero_element(v, ep);
-            }
+            for (int k = 0; k < 10; ++k)
+                ep[k] = v.e2p[10 * (size_t)id + k];
+            v.mask[id] = u;
+            if (u)
+                store_element(v, id, v.T[id], ep);
+            else
+                zero_element(v, ep);
         }
     }
 }
@@ -557,13 +628,20 @@ __global__ __launch_bounds__(kBlock) void k_edits(DevView v, const int32_t* __re
                                                   const int32_t* __restrict__ n_dev)
 {
     __shared__ int s_bits;
-    bool bad_n;
-    const int n = frame_count(n_host, n_dev, bad_n);
     const int gt = blockIdx.x * kBlock + threadIdx.x;
     const int i = gt / kEditLanes;
+    // the edit itself is read while the device-side count is still in flight
+    int id = -1;
+    unsigned st = 0;
+    if (i < n_host) {
+        id = ids[i];
+        st = states[i];
+    }
+    bool bad_n;
+    const int n = frame_count(n_host, n_dev, bad_n);
     int bits = (bad_n && gt == 0) ? ERR_RANGE : 0;
     if (i < n)
-        bits |= edit_lane(v, ids, states, i, gt - i * kEditLanes);
+        bits |= edit_lane(v, id, st, i, gt - i * kEditLanes);
     bits = block_or(bits, &s_bits);
     if (threadIdx.x == 0)
         v.wg_err[blockIdx.x] = (uint8_t)bits;
@@ -575,15 +653,24 @@ __global__ __launch_bounds__(kBlock) void k_touched(DevView v, const int32_t* __
                                                     const int32_t* __restrict__ n_dev)
 {
     __shared__ int s_bits;
-    bool bad_n;
-    const int n = frame_count(n_host, n_dev, bad_n);
-    const int fe = frame_error(v, n > 0 ? (n * kEditLanes + kBlock - 1) / kBlock : 1, &s_bits);
-    publish_frame(v, fe, n);
     constexpr int L = Phase2<QD, QO>::kLanes;
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int i = (int)(t / L);
-    if (i < n)
-        touched_lane<QD, QO>(v, ids, fe, i, (int)(t - (int64_t)i * L));
+    const int r = (int)(t - (int64_t)i * L);
+    int j, vi, q;
+    const bool lane = touched_slot<QD, QO>(r, j, vi, q) && i < n_host;
+    // claim record and tet id load together with the count and the error
+    // bytes; lanes without them read fixed empty values instead, so the loads
+    // need no branch (whose join would wait for them)
+    const BlockDesc d = load_desc(lane ? v.rec + 10 * (size_t)i + j : &kNoClaim);
+    const int id = *(lane && r == 0 ? ids + i : &kNoTet);
+    bool bad_n;
+    const int n = frame_count(n_host, n_dev, bad_n);
+    // every workgroup of the edit phase's grid (sized by n_host) wrote its byte
+    const int fe = frame_error(v, n_host > 0 ? (n_host * kEditLanes + kBlock - 1) / kBlock : 1, &s_bits);
+    publish_frame(v, fe, n);
+    if (lane && i < n)
+        touched_lane<QD, QO>(v, d, id, fe, i, r, vi, q);
 }
 
 // Grid-wide barrier for a co-resident grid (the host sizes the grid from the
@@ -638,7 +725,7 @@ __global__ __launch_bounds__(kBlock) void k_frame(DevView v, const int32_t* __re
     int bits = (bad_n && t0 == 0) ? ERR_RANGE : 0;
     for (int64_t t = t0; t < (int64_t)n * kEditLanes; t += stride) {
         const int i = (int)(t / kEditLanes);
-        bits |= edit_lane(v, ids, states, i, (int)(t - (int64_t)i * kEditLanes));
+        bits |= edit_lane(v, ids[i], states[i], i, (int)(t - (int64_t)i * kEditLanes));
     }
     bits = block_or(bits, &s_bits);
     if (threadIdx.x == 0)
@@ -650,7 +737,10 @@ __global__ __launch_bounds__(kBlock) void k_frame(DevView v, const int32_t* __re
     constexpr int L = Phase2<QD, QO>::kLanes;
     for (int64_t t = t0; t < (int64_t)n * L; t += stride) {
         const int i = (int)(t / L);
-        touched_lane<QD, QO>(v, ids, fe, i, (int)(t - (int64_t)i * L));
+        const int r = (int)(t - (int64_t)i * L);
+        int j, vi, q;
+        if (touched_slot<QD, QO>(r, j, vi, q))
+            touched_lane<QD, QO>(v, load_desc(v.rec + 10 * (size_t)i + j), r == 0 ? ids[i] : -1, fe, i, r, vi, q);
     }
 }
 
@@ -675,11 +765,14 @@ inline unsigned blocks_for(int64_t threads)
 
 }  // namespace
 
-hipError_t launch_element(const DevView& v, hipStream_t s)
+hipError_t launch_element(const DevView& v, bool nt, hipStream_t s)
 {
     if (v.n_tets == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_element, dim3(blocks_for(v.n_tets)), dim3(kBlock), 0, s, v);
+    if (nt)
+        hipLaunchKernelGGL(k_element<true>, dim3(blocks_for(v.n_tets)), dim3(kBlock), 0, s, v);
+    else
+        hipLaunchKernelGGL(k_element<false>, dim3(blocks_for(v.n_tets)), dim3(kBlock), 0, s, v);
     return hipGetLastError();
 }
 
@@ -691,10 +784,15 @@ hipError_t launch_reduce_all(const DevView& v, const MapConfig& m, hipStream_t s
     const int64_t threads = diag_lanes + (int64_t)v.no * 9 * m.qo;
     if (v.nd + v.no == 0)
         return hipSuccess;
-#define LAUNCH(QD, QO)                                                                                   \
-    if (m.qd == QD && m.qo == QO) {                                                                      \
-        hipLaunchKernelGGL((k_reduce_all<QD, QO>), dim3(blocks_for(threads)), dim3(kBlock), 0, s, v, diag_lanes); \
-        return hipGetLastError();                                                                        \
+#define LAUNCH(QD, QO)                                                                                    \
+    if (m.qd == QD && m.qo == QO) {                                                                       \
+        if (m.nt)                                                                                         \
+            hipLaunchKernelGGL((k_reduce_all<QD, QO, true>), dim3(blocks_for(threads)), dim3(kBlock), 0, s, v, \
+                               diag_lanes);                                                               \
+        else                                                                                              \
+            hipLaunchKernelGGL((k_reduce_all<QD, QO, false>), dim3(blocks_for(threads)), dim3(kBlock), 0, s, v, \
+                               diag_lanes);                                                               \
+        return hipGetLastError();                                                                         \
     }
     STA_MAPPINGS(LAUNCH)
 #undef LAUNCH

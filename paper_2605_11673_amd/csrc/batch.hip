@@ -28,13 +28,13 @@ sta_status tune_fail(sta_ctx* ctx, sta_status code, const std::string& msg)
 }
 
 struct Cfg {
-    int fused, rqd, rqo, sqd, sqo, cap;
+    int fused, rqd, rqo, sqd, sqo, cap, nt;
 };
 
 std::string cache_key(const sta_ctx* ctx, int64_t n_edits)
 {
     char buf[256];
-    std::snprintf(buf, sizeof buf, "stafem-tune-v1 %lld %lld %lld %lld %lld %lld", (long long)ctx->n_nodes,
+    std::snprintf(buf, sizeof buf, "stafem-tune-v2 %lld %lld %lld %lld %lld %lld", (long long)ctx->n_nodes,
                   (long long)ctx->n_tets, (long long)ctx->nnz, (long long)ctx->nd, (long long)ctx->no,
                   (long long)n_edits);
     return buf;
@@ -55,7 +55,8 @@ bool cache_lookup(const char* path, const std::string& key, Cfg& c)
         while (!k.empty() && k.back() == ' ')
             k.pop_back();
         Cfg t;
-        if (k == key && std::sscanf(bar + 1, "%d %d %d %d %d %d", &t.fused, &t.rqd, &t.rqo, &t.sqd, &t.sqo, &t.cap) == 6) {
+        if (k == key && std::sscanf(bar + 1, "%d %d %d %d %d %d %d", &t.fused, &t.rqd, &t.rqo, &t.sqd, &t.sqo, &t.cap,
+                                    &t.nt) == 7) {
             c = t;  // the last matching line wins
             found = true;
         }
@@ -69,7 +70,7 @@ void cache_store(const char* path, const std::string& key, const Cfg& c)
     FILE* f = std::fopen(path, "a");
     if (!f)
         return;
-    std::fprintf(f, "%s | %d %d %d %d %d %d\n", key.c_str(), c.fused, c.rqd, c.rqo, c.sqd, c.sqo, c.cap);
+    std::fprintf(f, "%s | %d %d %d %d %d %d %d\n", key.c_str(), c.fused, c.rqd, c.rqo, c.sqd, c.sqo, c.cap, c.nt);
     std::fclose(f);
 }
 
@@ -160,9 +161,9 @@ sta_status sta_autotune(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* sta
         return st;
     };
     if (cache && cache_lookup(cache, key, best)) {
-        sta_status st = sta_set_config(ctx, best.fused, best.rqd, best.rqo, best.sqd, best.sqo, best.cap);
-        std::snprintf(line, sizeof line, "cached %s: fused %d rebuild %dx%d stream %dx%d cap %d\n", cache,
-                      best.fused, best.rqd, best.rqo, best.sqd, best.sqo, best.cap);
+        sta_status st = sta_set_config(ctx, best.fused, best.rqd, best.rqo, best.sqd, best.sqo, best.cap, best.nt);
+        std::snprintf(line, sizeof line, "cached %s: fused %d rebuild %dx%d nt %d stream %dx%d cap %d\n", cache,
+                      best.fused, best.rqd, best.rqo, best.nt, best.sqd, best.sqo, best.cap);
         rep += line;
         return finish(st);
     }
@@ -208,7 +209,7 @@ sta_status sta_autotune(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* sta
         return tune_fail(ctx, STA_ENOMEM, "autotune workspace");
     }
     const Cfg saved{ctx->fused, ctx->rebuild_map.qd, ctx->rebuild_map.qo, ctx->stream_map.qd, ctx->stream_map.qo,
-                    ctx->frame_grid_cap};
+                    ctx->frame_grid_cap, ctx->rebuild_map.nt};
     const int saved_timing = ctx->timing;
     ctx->timing = false;
     sta_status st = STA_OK;
@@ -216,8 +217,9 @@ sta_status sta_autotune(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* sta
     // 1. rebuild mapping
     double best_t = 1e30;
     best = saved;
+    for (int nt = 0; nt <= 1; ++nt)
     for (auto& m : kMaps) {
-        sta_set_config(ctx, saved.fused, m[0], m[1], saved.sqd, saved.sqo, saved.cap);
+        sta_set_config(ctx, saved.fused, m[0], m[1], saved.sqd, saved.sqo, saved.cap, nt);
         std::vector<float> t;
         for (int r = 0; r <= reps && st == STA_OK; ++r) {
             float ms = 0.0f;
@@ -230,12 +232,13 @@ sta_status sta_autotune(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* sta
                 t.push_back(ms);
         }
         const double med = median(t) * 1e3;
-        std::snprintf(line, sizeof line, "rebuild  map %2dx%d: %9.2f us\n", m[0], m[1], med);
+        std::snprintf(line, sizeof line, "rebuild  map %2dx%d nt %d: %9.2f us\n", m[0], m[1], nt, med);
         rep += line;
         if (med < best_t) {
             best_t = med;
             best.rqd = m[0];
             best.rqo = m[1];
+            best.nt = nt;
         }
     }
 
@@ -245,7 +248,7 @@ sta_status sta_autotune(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* sta
     for (int fused = 0; fused <= 1 && st == STA_OK; ++fused)
         for (auto& m : kMaps)
             for (int ci = 0; ci < (fused ? 3 : 1) && st == STA_OK; ++ci) {
-                sta_set_config(ctx, fused, best.rqd, best.rqo, m[0], m[1], caps[ci]);
+                sta_set_config(ctx, fused, best.rqd, best.rqo, m[0], m[1], caps[ci], best.nt);
                 std::vector<float> t;
                 for (int r = 0; r <= reps && st == STA_OK; ++r) {
                     float ms = 0.0f;
@@ -273,14 +276,14 @@ sta_status sta_autotune(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* sta
             }
     ctx->timing = saved_timing;
     if (st == STA_OK && hipStreamSynchronize(s) == hipSuccess && sta_status_sync(ctx, stream) == STA_OK) {
-        sta_set_config(ctx, best.fused, best.rqd, best.rqo, best.sqd, best.sqo, best.cap);
-        std::snprintf(line, sizeof line, "chosen: fused %d rebuild %dx%d stream %dx%d cap %d\n", best.fused,
-                      best.rqd, best.rqo, best.sqd, best.sqo, best.cap);
+        sta_set_config(ctx, best.fused, best.rqd, best.rqo, best.sqd, best.sqo, best.cap, best.nt);
+        std::snprintf(line, sizeof line, "chosen: fused %d rebuild %dx%d nt %d stream %dx%d cap %d\n", best.fused,
+                      best.rqd, best.rqo, best.nt, best.sqd, best.sqo, best.cap);
         rep += line;
         if (cache)
             cache_store(cache, key, best);
     } else {
-        sta_set_config(ctx, saved.fused, saved.rqd, saved.rqo, saved.sqd, saved.sqo, saved.cap);
+        sta_set_config(ctx, saved.fused, saved.rqd, saved.rqo, saved.sqd, saved.sqo, saved.cap, saved.nt);
         if (st == STA_OK)
             st = STA_EHIP;
     }

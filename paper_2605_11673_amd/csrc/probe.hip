@@ -1,0 +1,134 @@
+// Latency probe: the floor under which a streaming frame cannot go on this
+// GPU, measured rather than assumed.  One lane walks a dependent chain
+// (each address comes from the previous load) and reads the 100 MHz
+// real-time counter around it; the same for a chain of returning atomics.
+// Together with the duration of an empty kernel this bounds a frame built
+// from two launches of a few dependent memory round trips each.
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "sta_internal.h"
+
+namespace sta {
+
+namespace {
+
+// chase[i] = (i + stride) mod n, stride coprime with n and larger than a
+// cache line, so consecutive hops hit different lines.
+__global__ void k_chase_init(uint32_t* chase, uint32_t n, uint32_t stride)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        chase[i] = (uint32_t)(((uint64_t)i + stride) % n);
+}
+
+__global__ void k_chase(const uint32_t* __restrict__ chase, int hops, uint64_t* out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    uint32_t p = 0;
+    for (int h = 0; h < 16; ++h)  // warm up along the start of the walk
+        p = chase[p];
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    for (int h = 0; h < hops; ++h)
+        p = chase[p];
+    const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
+    out[0] = t1 - t0;
+    out[1] = p;  // keeps the chain live
+}
+
+// A chain of returning device-scope atomics: each target depends on the previous result.
+__global__ void k_atomic_chain(uint32_t* __restrict__ chase, int hops, uint64_t* out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    uint32_t p = 0;
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    for (int h = 0; h < hops; ++h)
+        p = atomicAdd(chase + p, 0u);
+    const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
+    out[0] = t1 - t0;
+    out[1] = p;
+}
+
+__global__ void k_empty() {}
+
+}  // namespace
+
+}  // namespace sta
+
+using namespace sta;
+
+extern "C" sta_status sta_latency_probe(void* stream, double* out4)
+{
+    if (!out4)
+        return STA_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint32_t n_big = 64u << 20;  // 256 MB of uint32: beyond L2 and the 256 MB Infinity Cache working set
+    const uint32_t n_small = 256u << 10;  // 1 MB: L2 resident
+    uint32_t *big = nullptr, *small = nullptr;
+    uint64_t* dout = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipMalloc(&big, sizeof(uint32_t) * n_big);
+    if (e == hipSuccess) e = hipMalloc(&small, sizeof(uint32_t) * n_small);
+    if (e == hipSuccess) e = hipMalloc(&dout, 2 * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    const int hops = 2000;
+    uint64_t h[2] = {0, 0};
+    double res[4] = {0, 0, 0, 0};
+    if (e == hipSuccess) {
+        // strides of ~4 KB-2 MB so each hop lands on a new line (and mostly a new page)
+        hipLaunchKernelGGL(k_chase_init, dim3(n_big / 256), dim3(256), 0, s, big, n_big, 1000003u);
+        hipLaunchKernelGGL(k_chase_init, dim3(n_small / 256), dim3(256), 0, s, small, n_small, 1031u);
+        e = hipStreamSynchronize(s);
+    }
+    // [1] dependent load, working set far beyond the caches
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_chase, dim3(1), dim3(64), 0, s, big, hops, dout);
+        e = hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        res[1] = (double)h[0] * 10.0 / hops;  // 100 MHz ticks -> ns per hop
+    }
+    // [2] dependent load, L2-resident (second walk over a 1 MB buffer)
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_chase, dim3(1), dim3(64), 0, s, small, hops, dout);
+        hipLaunchKernelGGL(k_chase, dim3(1), dim3(64), 0, s, small, hops, dout);
+        e = hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        res[2] = (double)h[0] * 10.0 / hops;
+    }
+    // [3] dependent returning atomics on the L2-sized buffer
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_atomic_chain, dim3(1), dim3(64), 0, s, small, hops, dout);
+        e = hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        res[3] = (double)h[0] * 10.0 / hops;
+    }
+    // [0] an empty kernel, launch to completion, averaged over back-to-back launches
+    if (e == hipSuccess) {
+        const int reps = 200;
+        hipLaunchKernelGGL(k_empty, dim3(1), dim3(64), 0, s);
+        e = hipEventRecord(a, s);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) {
+            hipLaunchKernelGGL(k_empty, dim3(1), dim3(64), 0, s);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        res[0] = ms * 1e3 / reps;  // us per back-to-back empty kernel
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (big) (void)hipFree(big);
+    if (small) (void)hipFree(small);
+    if (dout) (void)hipFree(dout);
+    if (e != hipSuccess)
+        return STA_EHIP;
+    for (int k = 0; k < 4; ++k)
+        out4[k] = res[k];
+    return STA_OK;
+}

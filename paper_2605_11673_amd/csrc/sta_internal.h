@@ -35,6 +35,7 @@ struct Ctl {
 // (1 thread-, 4 quad-, 16 wave-sixteenth-per-slot; diagonal 1/4/16, off 1/4).
 struct MapConfig {
     int qd = 1, qo = 1;
+    int nt = 0;  // non-temporal cache hints (rebuild only)
 };
 
 // Material constants, evaluated once on the host in the fixed order.
@@ -147,7 +148,7 @@ struct sta_ctx {
 namespace sta {
 
 // Kernel launchers (assembly.hip).
-hipError_t launch_element(const DevView& v, hipStream_t s);
+hipError_t launch_element(const DevView& v, bool nt, hipStream_t s);
 hipError_t launch_reduce_all(const DevView& v, const MapConfig& m, hipStream_t s);
 // Streaming phases.  n_dev (device int32, may be NULL) overrides n_host, which
 // then only sizes the grid (an upper bound on the edit count).

@@ -57,11 +57,12 @@ SIGNATURES = {
     "sta_adjoint": (_int, [_vp, _vp, _vp, _vp, _vp]),
     "sta_slot_outer": (_int, [_vp, _vp, _vp, _dbl, _vp, _vp]),
     "sta_cg_solve": (_int, [_vp, _vp, _vp, _vp, _dbl, _int, _vp, ctypes.POINTER(_int), ctypes.POINTER(_dbl)]),
-    "sta_set_config": (_int, [_vp, _int, _int, _int, _int, _int, _int]),
+    "sta_set_config": (_int, [_vp, _int, _int, _int, _int, _int, _int, _int]),
     "sta_get_config": (_int, [_vp, ctypes.POINTER(_int)]),
     "sta_autotune": (_int, [_vp, _vp, _vp, _i64, _int, _vp, ctypes.c_char_p, _i64]),
     "sta_batch_build": (_int, [_int, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _dbl, _vp, _vp, ctypes.POINTER(_vp)]),
     "sta_batch_offsets": (_int, [_vp, ctypes.POINTER(_int), _vp, _vp, _vp, _vp, _i64]),
+    "sta_latency_probe": (_int, [_vp, ctypes.POINTER(_dbl)]),
     "sta_status_sync": (_int, [_vp, _vp]),
     "sta_last_error": (ctypes.c_char_p, [_vp]),
     "sta_destroy": (None, [_vp]),
@@ -261,14 +262,14 @@ class Assembler:
                                    ctypes.byref(it), ctypes.byref(rr)), self._ctx)
         return x, it.value, rr.value
 
-    CONFIG = ("fused", "rebuild_qd", "rebuild_qo", "stream_qd", "stream_qo", "grid_cap")
+    CONFIG = ("fused", "rebuild_qd", "rebuild_qo", "stream_qd", "stream_qo", "grid_cap", "rebuild_nt")
 
-    def set_config(self, fused=0, rebuild_qd=1, rebuild_qo=1, stream_qd=1, stream_qo=1, grid_cap=0):
+    def set_config(self, fused=0, rebuild_qd=1, rebuild_qo=1, stream_qd=1, stream_qo=1, grid_cap=0, rebuild_nt=0):
         _check(load().sta_set_config(self._ctx, int(fused), int(rebuild_qd), int(rebuild_qo), int(stream_qd),
-                                     int(stream_qo), int(grid_cap)), self._ctx)
+                                     int(stream_qo), int(grid_cap), int(rebuild_nt)), self._ctx)
 
     def get_config(self) -> dict:
-        out = (ctypes.c_int * 6)()
+        out = (ctypes.c_int * 7)()
         _check(load().sta_get_config(self._ctx, out), self._ctx)
         return dict(zip(self.CONFIG, list(out)))
 
@@ -337,6 +338,14 @@ class Batch(Assembler):
     def from_workloads(cls, ws, stream=None):
         w0 = ws[0]
         return cls([(w.x, w.tets, w.E, w.mask0) for w in ws], w0.nu, w0.rho, w0.dt, stream)
+
+
+def latency_probe(stream=None) -> dict:
+    """Measured latency floor of the GPU (see sta_latency_probe)."""
+    out = (ctypes.c_double * 4)()
+    _check(load().sta_latency_probe(_stream_handle(stream), out), None)
+    return {"empty_kernel_us": out[0], "dependent_load_256MB_ns": out[1], "dependent_load_l2_ns": out[2],
+            "dependent_atomic_ns": out[3]}
 
 
 def upload_frame(ids: np.ndarray, states: np.ndarray, device="cuda"):

@@ -49,7 +49,7 @@ def test_mappings_and_modes_bitwise(qd, qo, fused):
         frames = list(w.frames) + ([] if "refine" in w.name else W.merge_stream(w.frames))
         pat = oracle.pattern(w.n_nodes, w.tets)
         asm = Sm.Assembler.from_workload(w)
-        asm.set_config(fused=fused, rebuild_qd=qd, rebuild_qo=qo, stream_qd=qd, stream_qo=qo)
+        asm.set_config(fused=fused, rebuild_qd=qd, rebuild_qo=qo, stream_qd=qd, stream_qo=qo, rebuild_nt=fused)
         asm.full_rebuild()
         check(host_values(asm), oracle.rebuild_workload(w, w.mask0, pat), f"{w.name} rebuild {qd}x{qo}")
         mask = w.mask0.copy()
