@@ -4,12 +4,13 @@ Plain, slow, obviously-correct reference for what the GPU path computes:
 the superset sparsity pattern, the rebuild of A_t = M_t + dt^2 K_t from the
 current active mask (paper Sec. 3.3 invariant, Sec. 3.4 eq. (8)), the
 gradient of an objective through the assembled values, and a Jacobi-PCG
-solve (Sec. 4).
+solve (Sec. 4); and, in ``proxy.py``, the graph-Laplacian proxy operator of
+Sec. 3.1 (edge multiplicities, binary edge activity, L_t + eps I).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It shares no code with the GPU
 library: the arithmetic lives in ``oracle.c`` (built with gcc, contraction
-off), the pattern in ``pattern.py`` (numpy).
+off), the patterns in ``pattern.py`` and ``proxy.py`` (numpy).
 
 Functions whose parity has no external pin are marked "parity unpinned" in
 their docstring; at present every function is pinned by a test in

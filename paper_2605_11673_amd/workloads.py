@@ -36,6 +36,9 @@ RHO = 1000.0
 DT = 1e-2
 E_MEDIAN = 1e5
 LOGE_SIGMA = 0.5
+# Diagonal shift of the proxy system A_t = L_t + eps I; the paper asks only for a
+# small positive value.
+PROXY_EPS = 1e-6
 
 # Permutations of the three axes in lexicographic order; tet p of a cell walks
 # from the cell origin along axes PERMS[p][0], PERMS[p][1], PERMS[p][2].
