@@ -263,6 +263,95 @@ const char* sta_last_error(const sta_ctx* ctx);
 /* Free everything the context owns.  NULL is ignored. */
 void sta_destroy(sta_ctx* ctx);
 
+/* ------------------------------------------------------------------------
+ * Graph-Laplacian proxy operator (Sec. 3.1 eqs. (1)-(4), Sec. 3.2 eq. (7),
+ * Sec. 3.3 maintained state, Alg. 1), on its own context.
+ *
+ *   c_t(u,v) = number of active tets with edge (u,v)          (eq. (1))
+ *   a_t(u,v) = 1 if c_t(u,v) > 0 else 0                        (eq. (2))
+ *   A_t      = L_t + eps I: off-diagonal -a_t(u,v), diagonal the number of
+ *              active edges at u, plus eps                     (eqs. (3), (4))
+ *
+ * Layout: scalar CSR over n rows, int32 indices; row u holds the diagonal
+ * and one entry per superset edge at u (columns ascending), for every
+ * vertex in some candidate tet (other rows are empty).  The pattern never
+ * changes: an inactive edge's two entries hold +0.0, an active one's -1.0;
+ * a diagonal holds float64(degree) + eps.  Edges are numbered in ascending
+ * (u, v), u < v.  Counts and degrees are maintained as int32 with the +1/-1
+ * deltas of eq. (7); values are rewritten from them, so every frame leaves
+ * the state exactly equal to sta_proxy_full_rebuild on the same mask.
+ * Stream, error and threading rules as above.
+ * ------------------------------------------------------------------------ */
+typedef struct sta_proxy sta_proxy;
+
+/* Build the scalar superset pattern, the edge incidence and A_0 (Alg. 1
+ * initialisation).  tets host n_tets*4 int32 (4 distinct ids in
+ * [0, n_nodes)), mask0 host n_tets uint8 in {0, 1}, eps finite >= 0.
+ * Inputs are copied.  Synchronises `stream`.  Errors: STA_EINVAL,
+ * STA_EDEGENERATE (repeated vertex), STA_ENOMEM, STA_EHIP; *out = NULL. */
+sta_status sta_proxy_build(const int32_t* tets, int64_t n_nodes, int64_t n_tets, const uint8_t* mask0, double eps,
+                           void* stream, sta_proxy** out);
+
+/* Policy full_rebuild (Sec. 3.5): counts from the mask over each edge's
+ * incidence list, then degrees and every value.  Asynchronous. */
+sta_status sta_proxy_full_rebuild(sta_proxy* p, void* stream);
+
+/* One frame of Alg. 1: edit k sets tet ids_dev[k] to states_dev[k] (device
+ * int32 / uint8, n_edits of each, ids distinct).  Each changed tet adds +1
+ * (activation) or -1 (deletion) to its six edge counts; a count moving
+ * between 0 and > 0 inserts or removes the edge's two entries and moves both
+ * endpoint degrees; then the entries and diagonals of changed tets are
+ * rewritten.  Asynchronous.  Bad ids / states / duplicates found on the
+ * device roll the frame back (sta_proxy_status_sync reports them).  Host
+ * errors: STA_EINVAL. */
+sta_status sta_proxy_apply_edits(sta_proxy* p, const int32_t* ids_dev, const uint8_t* states_dev, int64_t n_edits,
+                                 void* stream);
+
+/* As sta_proxy_apply_edits with the edit count read from *n_dev (device
+ * int32) and the arrays holding `capacity` entries (1 <= capacity <=
+ * n_tets): graph-capturable.  *n_dev outside [0, capacity] is STA_ERANGE. */
+sta_status sta_proxy_apply_edits_dev(sta_proxy* p, const int32_t* ids_dev, const uint8_t* states_dev,
+                                     int64_t capacity, const int32_t* n_dev, void* stream);
+
+/* n_rows (= n_nodes), nnz and the number of superset edges (any may be NULL). */
+sta_status sta_proxy_sizes(const sta_proxy* p, int64_t* n_rows, int64_t* nnz, int64_t* n_edges);
+
+/* Borrowed device pointers, valid until sta_proxy_destroy: the nnz values,
+ * c_t per edge (int32), the degree per vertex (int32). */
+const double* sta_proxy_values_ptr(const sta_proxy* p);
+const int32_t* sta_proxy_counts_ptr(const sta_proxy* p);
+const int32_t* sta_proxy_degree_ptr(const sta_proxy* p);
+
+/* Stream-ordered device-to-device copies of the current state into caller
+ * buffers (any may be NULL): values (nnz float64), counts (n_edges int32),
+ * degree (n_rows int32). */
+sta_status sta_proxy_copy_state(const sta_proxy* p, double* values, int32_t* counts, int32_t* degree, void* stream);
+
+/* Borrowed device pointers to the CSR (rowptr n+1, colidx nnz) and the edge
+ * list (2 int32 per edge: u < v). */
+sta_status sta_proxy_pattern_ptrs(const sta_proxy* p, const int32_t** rowptr, const int32_t** colidx,
+                                  const int32_t** edges);
+
+/* Host copies of the same (synchronous): rowptr n_rows+1, colidx nnz,
+ * edges 2*n_edges int32. */
+sta_status sta_proxy_pattern_host(const sta_proxy* p, int32_t* rowptr, int32_t* colidx, int32_t* edges);
+
+/* Synchronises `stream`; out3 = {edit count of the last frame, edits that
+ * changed a tet's state, edge transitions between 0 and > 0} (0, 0 if the
+ * frame was rolled back). */
+sta_status sta_proxy_last_frame_stats(sta_proxy* p, void* stream, int64_t* out3);
+
+/* Synchronise `stream`, return and clear the device-recorded error
+ * (STA_ERANGE, STA_EDUP), else STA_OK. */
+sta_status sta_proxy_status_sync(sta_proxy* p, void* stream);
+
+/* Message for the last error on p (or of the last failed sta_proxy_build
+ * when p is NULL).  Never NULL. */
+const char* sta_proxy_last_error(const sta_proxy* p);
+
+/* Free everything p owns.  NULL is ignored. */
+void sta_proxy_destroy(sta_proxy* p);
+
 #ifdef __cplusplus
 }
 #endif

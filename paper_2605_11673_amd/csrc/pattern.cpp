@@ -8,12 +8,13 @@
 // contribute to it in ascending tet id; this order is the summation order of
 // every entry, in the rebuild and in the streaming update alike.
 //
-// CSR.  Row 3i+p has the columns 3j+q of every neighbour j of i (i itself
-// included) in ascending order, so rows 3i, 3i+1, 3i+2 share one column list
-// of length 3*deg(i).  A block's 9 values therefore sit at
+// CSR, for node blocks of size bs (3 for elasticity, 1 for the scalar proxy
+// operator).  Row bs*i+p has the columns bs*j+q of every neighbour j of i
+// (i itself included) in ascending order, so the bs rows of node i share one
+// column list of length bs*deg(i).  A block's values therefore sit at
 //   up + p*rowlen(i) + q            (upper block, row node i)
 //   lo + q*rowlen(j) + p            (its mirror, row node j)
-// with up / lo the CSR index of entry (3i,3j) / (3j,3i).
+// with up / lo the CSR index of entry (bs*i,bs*j) / (bs*j,bs*i).
 #include <algorithm>
 #include <cstring>
 
@@ -26,7 +27,7 @@ const int kPairA[6] = {0, 0, 0, 1, 1, 2};
 const int kPairB[6] = {1, 2, 3, 2, 3, 3};
 }  // namespace
 
-std::string build_host_pattern(int64_t n, const int32_t* tets, int64_t m, HostPattern& P)
+std::string build_host_pattern(int64_t n, const int32_t* tets, int64_t m, HostPattern& P, int bs)
 {
     // diagonal blocks: used nodes in ascending id
     std::vector<int32_t> did(n, -1);
@@ -122,23 +123,23 @@ std::string build_host_pattern(int64_t n, const int32_t* tets, int64_t m, HostPa
     // CSR
     int64_t nnz = 0;
     for (int64_t i = 0; i < n; ++i)
-        nnz += 9 * (aoff[i + 1] - aoff[i]);
+        nnz += (int64_t)bs * bs * (aoff[i + 1] - aoff[i]);
     if (nnz > INT32_MAX)
         return "pattern has more than 2^31-1 entries";
     P.nnz = nnz;
-    P.rowptr.assign((size_t)3 * n + 1, 0);
+    P.rowptr.assign((size_t)bs * n + 1, 0);
     P.colidx.assign((size_t)nnz, 0);
     int64_t at = 0;
     for (int64_t i = 0; i < n; ++i) {
         const int64_t d = aoff[i + 1] - aoff[i];
-        for (int p = 0; p < 3; ++p) {
-            P.rowptr[3 * i + p] = (int32_t)at;
+        for (int p = 0; p < bs; ++p) {
+            P.rowptr[bs * i + p] = (int32_t)at;
             for (int64_t s = 0; s < d; ++s)
-                for (int q = 0; q < 3; ++q)
-                    P.colidx[at++] = 3 * adj[aoff[i] + s] + q;
+                for (int q = 0; q < bs; ++q)
+                    P.colidx[at++] = bs * adj[aoff[i] + s] + q;
         }
     }
-    P.rowptr[3 * n] = (int32_t)at;
+    P.rowptr[bs * n] = (int32_t)at;
 
     auto pos = [&](int64_t i, int64_t j) -> int64_t {
         auto b = adj.begin() + aoff[i], e = adj.begin() + aoff[i + 1];
@@ -149,16 +150,19 @@ std::string build_host_pattern(int64_t n, const int32_t* tets, int64_t m, HostPa
         if (did[i] < 0)
             continue;
         const int64_t b = did[i];
-        P.dmeta[2 * b + 0] = (int32_t)(P.rowptr[3 * i] + 3 * pos(i, i));
-        P.dmeta[2 * b + 1] = (int32_t)(3 * (aoff[i + 1] - aoff[i]));
+        P.dmeta[2 * b + 0] = (int32_t)(P.rowptr[bs * i] + bs * pos(i, i));
+        P.dmeta[2 * b + 1] = (int32_t)(bs * (aoff[i + 1] - aoff[i]));
     }
     P.ometa.assign((size_t)no * 4, 0);
+    P.opair.assign((size_t)no * 2, 0);
     for (int64_t b = 0; b < no; ++b) {
         const int64_t i = (int64_t)(okeys[b] >> 32), j = (int64_t)(okeys[b] & 0xffffffffu);
-        P.ometa[4 * b + 0] = (int32_t)(P.rowptr[3 * i] + 3 * pos(i, j));
-        P.ometa[4 * b + 1] = (int32_t)(3 * (aoff[i + 1] - aoff[i]));
-        P.ometa[4 * b + 2] = (int32_t)(P.rowptr[3 * j] + 3 * pos(j, i));
-        P.ometa[4 * b + 3] = (int32_t)(3 * (aoff[j + 1] - aoff[j]));
+        P.opair[2 * b + 0] = (int32_t)i;
+        P.opair[2 * b + 1] = (int32_t)j;
+        P.ometa[4 * b + 0] = (int32_t)(P.rowptr[bs * i] + bs * pos(i, j));
+        P.ometa[4 * b + 1] = (int32_t)(bs * (aoff[i + 1] - aoff[i]));
+        P.ometa[4 * b + 2] = (int32_t)(P.rowptr[bs * j] + bs * pos(j, i));
+        P.ometa[4 * b + 3] = (int32_t)(bs * (aoff[j + 1] - aoff[j]));
     }
     P.ndiag.assign(did.begin(), did.end());
     P.nd = nd;

@@ -188,9 +188,11 @@ struct HostPattern {
     std::vector<int32_t> dseg, dinc, oseg, oinc;
     std::vector<int32_t> dmeta;  // 2 per block
     std::vector<int32_t> ometa;  // 4 per block
+    std::vector<int32_t> opair;  // 2 per off-diagonal block: its nodes i < j
     std::vector<int32_t> e2b, e2p;  // 10 per element
     std::vector<int32_t> ndiag;     // per node: diagonal block id or -1
 };
-std::string build_host_pattern(int64_t n_nodes, const int32_t* tets, int64_t n_tets, HostPattern& P);
+// bs: rows per node (3: elasticity, 1: scalar proxy operator).
+std::string build_host_pattern(int64_t n_nodes, const int32_t* tets, int64_t n_tets, HostPattern& P, int bs = 3);
 
 }  // namespace sta

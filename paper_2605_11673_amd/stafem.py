@@ -66,6 +66,21 @@ SIGNATURES = {
     "sta_status_sync": (_int, [_vp, _vp]),
     "sta_last_error": (ctypes.c_char_p, [_vp]),
     "sta_destroy": (None, [_vp]),
+    "sta_proxy_build": (_int, [_vp, _i64, _i64, _vp, _dbl, _vp, ctypes.POINTER(_vp)]),
+    "sta_proxy_full_rebuild": (_int, [_vp, _vp]),
+    "sta_proxy_apply_edits": (_int, [_vp, _vp, _vp, _i64, _vp]),
+    "sta_proxy_apply_edits_dev": (_int, [_vp, _vp, _vp, _i64, _vp, _vp]),
+    "sta_proxy_sizes": (_int, [_vp, _i64p, _i64p, _i64p]),
+    "sta_proxy_values_ptr": (_vp, [_vp]),
+    "sta_proxy_counts_ptr": (_vp, [_vp]),
+    "sta_proxy_degree_ptr": (_vp, [_vp]),
+    "sta_proxy_copy_state": (_int, [_vp, _vp, _vp, _vp, _vp]),
+    "sta_proxy_pattern_ptrs": (_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
+    "sta_proxy_pattern_host": (_int, [_vp, _vp, _vp, _vp]),
+    "sta_proxy_last_frame_stats": (_int, [_vp, _vp, _i64p]),
+    "sta_proxy_status_sync": (_int, [_vp, _vp]),
+    "sta_proxy_last_error": (ctypes.c_char_p, [_vp]),
+    "sta_proxy_destroy": (None, [_vp]),
 }
 
 _lib = None
@@ -338,6 +353,103 @@ class Batch(Assembler):
     def from_workloads(cls, ws, stream=None):
         w0 = ws[0]
         return cls([(w.x, w.tets, w.E, w.mask0) for w in ws], w0.nu, w0.rho, w0.dt, stream)
+
+
+def _proxy_check(code: int, p=None):
+    if code != STA_OK:
+        msg = load().sta_proxy_last_error(p)
+        raise StafemError(code, msg.decode() if msg else "")
+
+
+class Proxy:
+    """The graph-Laplacian proxy operator A_t = L_t + eps I over a superset mesh
+    (sta_proxy_* in include/stafem.h).  tets (m, 4) int32 and mask0 (m,) uint8
+    are host arrays, copied into the context."""
+
+    def __init__(self, n_nodes, tets, mask0, eps, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the HIP assembly path needs an MI355X")
+        L = load()
+        tets = np.ascontiguousarray(tets, dtype=np.int32)
+        mask0 = np.ascontiguousarray(mask0, dtype=np.uint8)
+        self.n_nodes, self.n_tets, self.eps = int(n_nodes), int(tets.shape[0]), float(eps)
+        p = _vp()
+        _proxy_check(L.sta_proxy_build(tets.ctypes.data, self.n_nodes, self.n_tets, mask0.ctypes.data, self.eps,
+                                       _stream_handle(stream), ctypes.byref(p)), None)
+        self._p = p
+        r, z, e = _i64(), _i64(), _i64()
+        _proxy_check(L.sta_proxy_sizes(p, ctypes.byref(r), ctypes.byref(z), ctypes.byref(e)), p)
+        self.n_rows, self.nnz, self.n_edges = r.value, z.value, e.value
+
+    @classmethod
+    def from_workload(cls, w, eps, stream=None):
+        return cls(w.n_nodes, w.tets, w.mask0, eps, stream)
+
+    def close(self):
+        if getattr(self, "_p", None):
+            load().sta_proxy_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def full_rebuild(self, stream=None):
+        _proxy_check(load().sta_proxy_full_rebuild(self._p, _stream_handle(stream)), self._p)
+
+    def apply_edits(self, ids: torch.Tensor, states: torch.Tensor, stream=None):
+        if ids.dtype != torch.int32 or states.dtype != torch.uint8 or not ids.is_cuda or not states.is_cuda \
+                or ids.numel() != states.numel():
+            raise TypeError("ids int32 and states uint8 CUDA tensors of equal length")
+        _proxy_check(load().sta_proxy_apply_edits(self._p, _dev_ptr(ids), _dev_ptr(states), ids.numel(),
+                                                  _stream_handle(stream)), self._p)
+
+    def apply_edits_dev(self, ids: torch.Tensor, states: torch.Tensor, n: torch.Tensor, stream=None):
+        if ids.dtype != torch.int32 or states.dtype != torch.uint8 or n.dtype != torch.int32 \
+                or ids.numel() != states.numel():
+            raise TypeError("ids int32, states uint8 (equal length) and n int32 CUDA tensors")
+        _proxy_check(load().sta_proxy_apply_edits_dev(self._p, _dev_ptr(ids), _dev_ptr(states), ids.numel(),
+                                                      _dev_ptr(n), _stream_handle(stream)), self._p)
+
+    def state(self, stream=None):
+        """Copies of (values float64, counts int32, degree int32) as CUDA tensors, stream-ordered."""
+        v = torch.empty(self.nnz, dtype=torch.float64, device="cuda")
+        c = torch.empty(self.n_edges, dtype=torch.int32, device="cuda")
+        d = torch.empty(self.n_rows, dtype=torch.int32, device="cuda")
+        _proxy_check(load().sta_proxy_copy_state(self._p, _dev_ptr(v), _dev_ptr(c), _dev_ptr(d),
+                                                 _stream_handle(stream)), self._p)
+        return v, c, d
+
+    def pattern_ptrs(self):
+        rp, ci, ed = _vp(), _vp(), _vp()
+        _proxy_check(load().sta_proxy_pattern_ptrs(self._p, ctypes.byref(rp), ctypes.byref(ci), ctypes.byref(ed)),
+                     self._p)
+        return rp.value, ci.value, ed.value
+
+    def pattern(self):
+        """(rowptr, colidx, edges (n_edges, 2)) int32 numpy arrays."""
+        rp = np.empty(self.n_rows + 1, dtype=np.int32)
+        ci = np.empty(max(self.nnz, 1), dtype=np.int32)
+        ed = np.empty(max(2 * self.n_edges, 2), dtype=np.int32)
+        _proxy_check(load().sta_proxy_pattern_host(self._p, rp.ctypes.data, ci.ctypes.data, ed.ctypes.data), self._p)
+        return rp, ci[: self.nnz], ed[: 2 * self.n_edges].reshape(-1, 2)
+
+    def values_ptr(self) -> int:
+        return int(load().sta_proxy_values_ptr(self._p) or 0)
+
+    def last_frame_stats(self, stream=None) -> dict:
+        out = (ctypes.c_int64 * 3)()
+        _proxy_check(load().sta_proxy_last_frame_stats(self._p, _stream_handle(stream), out), self._p)
+        return {"edits": out[0], "changed": out[1], "transitions": out[2]}
+
+    def status_sync(self, stream=None) -> int:
+        return int(load().sta_proxy_status_sync(self._p, _stream_handle(stream)))
+
+    def last_error(self) -> str:
+        m = load().sta_proxy_last_error(self._p)
+        return m.decode() if m else ""
 
 
 def latency_probe(stream=None) -> dict:

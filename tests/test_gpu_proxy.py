@@ -1,0 +1,191 @@
+"""GPU proxy operator (sta_proxy_*) against the oracle rebuild, bit for bit.
+
+After every frame the GPU's edge counts, vertex degrees and CSR values must
+equal the oracle's rebuild from the current mask (paper Sec. 3.3 invariant
+for the proxy of Sec. 3.1); the per-frame transition count must equal the
+number of edges whose activity flipped.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import proxy as P
+from paper_2605_11673_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+EPS = W.PROXY_EPS
+
+
+def S():
+    from paper_2605_11673_amd import stafem
+    return stafem
+
+
+def bits(a):
+    return np.ascontiguousarray(a, dtype=np.float64).view(np.uint64)
+
+
+def state(px):
+    v, c, d = px.state()
+    torch.cuda.synchronize()
+    return v.cpu().numpy(), c.cpu().numpy(), d.cpu().numpy()
+
+
+def check(px, w, mask, pat, what):
+    v, c, d = state(px)
+    ov, oc, od = P.proxy_rebuild(w.n_nodes, w.tets, mask, EPS, pat)
+    assert np.array_equal(c, oc), f"{what}: counts differ at {np.nonzero(c != oc)[0][:5]}"
+    assert np.array_equal(d, od), f"{what}: degrees differ at {np.nonzero(d != od)[0][:5]}"
+    assert np.array_equal(bits(v), bits(ov)), f"{what}: values differ at {np.nonzero(bits(v) != bits(ov))[0][:5]}"
+    return oc
+
+
+def run_stream(w, frames, every=1, label=""):
+    Sm = S()
+    print(f"[proxy] {label}: {w.n_tets} tets, {len(frames)} frames", flush=True)
+    pat = P.proxy_pattern(w.n_nodes, w.tets)
+    px = Sm.Proxy.from_workload(w, EPS)
+    assert (px.n_rows, px.nnz, px.n_edges) == (w.n_nodes, len(pat[1]), len(pat[2]))
+    for got, want in zip(px.pattern(), pat):
+        assert np.array_equal(got, want)
+    mask = w.mask0.copy()
+    oc_prev = check(px, w, mask, pat, f"{label} build")
+    for t, (ids, st) in enumerate(frames):
+        px.apply_edits(*Sm.upload_frame(ids, st))
+        changed = int(np.sum(mask[ids] != st))
+        mask[ids] = st
+        if t % every == 0 or t == len(frames) - 1:
+            oc = check(px, w, mask, pat, f"{label} frame {t}")
+            stats = px.last_frame_stats()
+            flips = int(np.sum((oc > 0) != (oc_prev > 0)))
+            assert stats == {"edits": len(ids), "changed": changed, "transitions": flips}, (t, stats, flips)
+            oc_prev = oc
+        else:
+            oc_prev = P.multiplicity(w.n_nodes, w.tets, mask, pat[2])
+    assert px.status_sync() == Sm.STA_OK
+    return px, mask, pat
+
+
+def test_cube_every_frame_and_inverse():
+    """Unjittered 4^3 cube, 24 deletion frames then the same frames undone in reverse:
+    every frame bitwise; at the end the state equals the initial state (apply then
+    inverse apply gives the initial bits) and a GPU full rebuild changes nothing."""
+    w = W.make_cube(0)
+    frames = list(w.frames) + W.merge_stream(w.frames)
+    px, mask, pat = run_stream(w, frames, label="cube")
+    assert np.array_equal(mask, w.mask0)
+    v0 = state(px)
+    px.full_rebuild()
+    v1 = state(px)
+    assert all(np.array_equal(bits(a) if a.dtype == np.float64 else a, bits(b) if b.dtype == np.float64 else b)
+               for a, b in zip(v0, v1))
+    px.close()
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_small_meshes(seed):
+    """Tiny random meshes (unused vertices give empty rows, random vertex order and mask):
+    random toggles of random subsets, every frame."""
+    Sm = S()
+    w = W.random_small_mesh(seed)
+    g = np.random.default_rng(seed)
+    pat = P.proxy_pattern(w.n_nodes, w.tets)
+    px = Sm.Proxy.from_workload(w, EPS)
+    mask = w.mask0.copy()
+    check(px, w, mask, pat, "small build")
+    for t in range(6):
+        k = int(g.integers(0, w.n_tets + 1))
+        ids = np.sort(g.choice(w.n_tets, size=k, replace=False)).astype(np.int32)
+        st = g.integers(0, 2, size=k).astype(np.uint8)
+        px.apply_edits(*Sm.upload_frame(ids, st))
+        mask[ids] = st
+        check(px, w, mask, pat, f"small{seed} frame {t}")
+    assert px.status_sync() == Sm.STA_OK
+    px.close()
+
+
+def test_fracture_full_size_every_frame():
+    """40^3 cube (384,000 tets, 462,520 edges): 24 Voronoi fracture frames (50..2000
+    deletions) then their reinsertion, every frame bitwise against the oracle."""
+    w = W.make_fracture(seed=0)
+    px, _, _ = run_stream(w, list(w.frames) + W.merge_stream(w.frames), label="fracture 40")
+    px.close()
+
+
+def test_refinement_full_size():
+    """Red-refinement superset (432,000 tets): 24 refine frames (each swap: parent off,
+    8 children on) and their merge, checked every 4th frame and at the end."""
+    w = W.make_refinement(seed=0)
+    px, _, _ = run_stream(w, list(w.frames), every=4, label="refinement 20")
+    px.close()
+
+
+def test_errors_roll_back_and_noops():
+    Sm = S()
+    w = W.make_cube(1)
+    pat = P.proxy_pattern(w.n_nodes, w.tets)
+    px = Sm.Proxy.from_workload(w, EPS)
+    base = state(px)
+
+    def same_as_base(what):
+        now = state(px)
+        for a, b in zip(now, base):
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), what
+
+    px.apply_edits(*Sm.upload_frame(np.array([5, 17, 5], np.int32), np.zeros(3, np.uint8)))
+    assert px.status_sync() == Sm.STA_EDUP
+    same_as_base("duplicate rolled back")
+    px.apply_edits(*Sm.upload_frame(np.array([5, w.n_tets], np.int32), np.zeros(2, np.uint8)))
+    assert px.status_sync() == Sm.STA_ERANGE
+    same_as_base("range rolled back")
+    px.apply_edits(*Sm.upload_frame(np.array([5, 6], np.int32), np.array([0, 2], np.uint8)))
+    assert px.status_sync() == Sm.STA_ERANGE
+    same_as_base("bad state rolled back")
+    # no-op edits (already active) change nothing and count nothing
+    px.apply_edits(*Sm.upload_frame(np.array([3, 4], np.int32), np.ones(2, np.uint8)))
+    assert px.status_sync() == Sm.STA_OK
+    assert px.last_frame_stats() == {"edits": 2, "changed": 0, "transitions": 0}
+    same_as_base("no-op edits")
+    # empty frame
+    px.apply_edits(torch.zeros(0, dtype=torch.int32, device="cuda"), torch.zeros(0, dtype=torch.uint8, device="cuda"))
+    assert px.status_sync() == Sm.STA_OK and px.last_frame_stats()["edits"] == 0
+    same_as_base("empty frame")
+    with pytest.raises(Sm.StafemError):
+        px.apply_edits(*Sm.upload_frame(np.arange(w.n_tets + 1, dtype=np.int32) % w.n_tets,
+                                        np.zeros(w.n_tets + 1, np.uint8)))
+    check(px, w, w.mask0, pat, "after errors")
+    px.close()
+
+
+def test_graph_replay_device_count():
+    """sta_proxy_apply_edits_dev captured once into a HIP graph and replayed with each
+    frame's list written into the same buffers; every replay vs the oracle; a count
+    above the capacity is reported and changes nothing."""
+    Sm = S()
+    w = W.make_fracture(seed=1, n=12, counts=[30, 90, 200, 60, 10])
+    frames = list(w.frames) + W.merge_stream(w.frames)
+    pat = P.proxy_pattern(w.n_nodes, w.tets)
+    px = Sm.Proxy.from_workload(w, EPS)
+    cap = max(len(f[0]) for f in frames)
+    ids = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    st = torch.zeros(cap, dtype=torch.uint8, device="cuda")
+    n = torch.zeros(1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        px.apply_edits_dev(ids, st, n)
+    torch.cuda.synchronize()
+    mask = w.mask0.copy()
+    for t, (fi, fs) in enumerate(frames):
+        ids[:len(fi)].copy_(torch.from_numpy(fi.astype(np.int32)))
+        st[:len(fi)].copy_(torch.from_numpy(fs.astype(np.uint8)))
+        n.fill_(len(fi))
+        g.replay()
+        torch.cuda.synchronize()
+        mask[fi] = fs
+        check(px, w, mask, pat, f"graph frame {t}")
+    n.fill_(cap + 1)
+    g.replay()
+    assert px.status_sync() == Sm.STA_ERANGE
+    check(px, w, mask, pat, "after bad count")
+    px.close()
