@@ -357,6 +357,202 @@ def secondary(torch, name, asm, frames, n_tets, n_nodes, mask0, peak, args, desc
     return out
 
 
+def proxy_rebuild_bytes(n_edges, n_incidences, n_nodes, nnz):
+    """Algorithmic bytes of the proxy rebuild: per edge its segment bounds, incidence ids
+    and mask bytes, count write, two positions and two value writes; per vertex its row
+    bounds, diagonal position, the row's values, degree and diagonal writes."""
+    return (n_edges * (8 + 4 + 8 + 16) + n_incidences * (4 + 1)
+            + n_nodes * (8 + 4 + 4 + 8) + (nnz - n_nodes) * 8 + n_nodes * 8)
+
+
+def proxy_section(torch, stafem, w, frames, args):
+    """The graph-Laplacian proxy operator over the same mesh and stream: streaming state
+    bitwise equal to the GPU rebuild at every frame, the whole stream graph-timed, the
+    rebuild timed, and (unless disabled) the oracle's rebuild on the host."""
+    from paper_2605_11673_amd.workloads import PROXY_EPS as eps
+
+    px = stafem.Proxy.from_workload(w, eps)
+    dfr = [stafem.upload_frame(ids, st) for ids, st in frames]
+    # parity: streaming state vs a rebuild of a second context at every frame
+    ref = stafem.Proxy.from_workload(w, eps)
+    mism = 0
+    trans = []
+    for ids, st in dfr:
+        px.apply_edits(ids, st)
+        trans.append(px.last_frame_stats()["transitions"])
+        a = px.state()
+        ref.apply_edits(ids, st)
+        ref.full_rebuild()
+        b = ref.state()
+        torch.cuda.synchronize()
+        mism += int(not all(torch.equal(x.view(torch.uint8) if x.dtype == torch.float64 else x,
+                                        y.view(torch.uint8) if y.dtype == torch.float64 else y)
+                            for x, y in zip(a, b)))
+    ref.close()
+    # undo the stream so that each timed step starts from the initial state
+    for ids, st in reversed(dfr):
+        px.apply_edits(ids, (1 - st.to(torch.int32)).to(torch.uint8))
+    inv = [(ids, (1 - st.to(torch.int32)).to(torch.uint8)) for ids, st in dfr]
+    torch.cuda.synchronize()
+
+    def step():
+        for ids, st in dfr:
+            px.apply_edits(ids, st)
+        for ids, st in reversed(inv):
+            px.apply_edits(ids, st)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    g.replay()
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(args.steps):
+        g.replay()
+    ev[1].record()
+    torch.cuda.synchronize()
+    step_s = ev[0].elapsed_time(ev[1]) * 1e-3 / args.steps
+    frames_per_step = 2 * len(frames)
+    reb = []
+    for _ in range(max(5, args.reps)):
+        torch.cuda._sleep(200000)
+        ev[0].record()
+        px.full_rebuild()
+        ev[1].record()
+        ev[1].synchronize()
+        reb.append(ev[0].elapsed_time(ev[1]) * 1e3)
+    assert px.status_sync() == stafem.STA_OK
+    edits = int(sum(len(f[0]) for f in frames))
+    reb_us = float(np.median(reb))
+    alg = proxy_rebuild_bytes(px.n_edges, 6 * w.n_tets, w.n_nodes, px.nnz)
+    out = {"workload": f"graph-Laplacian proxy L_t + eps I (eps {eps:g}) over the 40^3 fracture mesh: the 48-frame "
+                       "fracture+reinsertion stream, then the same frames undone (96 frames per step)",
+           "n_edges": px.n_edges, "nnz": px.nnz, "frames_per_step": frames_per_step,
+           "edits_per_step": 2 * edits, "value": 2 * edits / step_s, "unit": "edits/s",
+           "ms_per_step": step_s * 1e3, "stream_pipelined_us_per_frame": round(step_s * 1e6 / frames_per_step, 3),
+           "transitions_per_stream": int(sum(trans)),
+           "rebuild_us_median": round(reb_us, 3),
+           "rebuild_roofline": {"bound": "hbm", "achieved": round(alg / (reb_us * 1e-6) / 1e9, 2), "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": round(alg / (reb_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5),
+                                "traffic": None, "algorithmic_bytes": alg},
+           "rebuild_vs_pipelined_frame": round(reb_us / (step_s * 1e6 / frames_per_step), 2),
+           "parity": {"frames_checked": len(frames), "mismatching_frames": mism,
+                      "check": "streaming counts, degrees and values bitwise equal to a GPU rebuild at every frame"}}
+    px.close()
+    if not args.no_cpu_baseline:
+        from oracle import proxy as oproxy
+
+        pat = oproxy.proxy_pattern(w.n_nodes, w.tets)
+        mask = w.mask0.copy()
+        t_total, k = 0.0, 0
+        for ids, st in frames[::8]:
+            mask[ids] = st
+            t0 = time.perf_counter()
+            oproxy.proxy_rebuild(w.n_nodes, w.tets, mask, eps, pat)
+            t_total += time.perf_counter() - t0
+            k += 1
+        out["cpu_baseline"] = {"value": round(t_total / k * 1e3, 3), "unit": "ms per rebuild", "cores": 1,
+                               "kind": "oracle", "sample": f"proxy oracle rebuild (numpy) at {k} frames of the stream"}
+    log(f"[bench] proxy: {step_s * 1e3:.3f} ms/step, {out['stream_pipelined_us_per_frame']} us/frame, "
+        f"rebuild {reb_us:.1f} us, parity mismatches {mism}")
+    return out
+
+
+def graph_time(torch, fn, steps, warmup):
+    """Seconds per call of fn() captured once as a HIP graph and replayed `steps` times."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    g.replay()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(steps):
+        g.replay()
+    ev[1].record()
+    torch.cuda.synchronize()
+    return ev[0].elapsed_time(ev[1]) * 1e-3 / steps, g
+
+
+def drift(torch, asm):
+    """Largest difference between the maintained values and a rebuild of the same mask
+    (the rebuild replaces the maintained values)."""
+    got = asm.values()
+    asm.full_rebuild()
+    ref = asm.values()
+    torch.cuda.synchronize()
+    d = (got - ref).abs()
+    nz = ref != 0
+    rel = (d[nz] / ref[nz].abs()).max().item() if bool(nz.any()) else 0.0
+    return {"max_abs": d.max().item(), "max_rel": rel, "entries_differing": int((d != 0).sum().item()),
+            "entries": int(ref.numel())}
+
+
+def delta_section(torch, stafem, w, frames, cfg, exact_step_s, args):
+    """The paper's +/- delta policy (sta_apply_edits_delta) on the headline stream and on a
+    repeated-locality stream (one slab deleted and reinserted frame after frame): time per
+    frame against the exact policy, and the drift from the rebuild after many frames."""
+    asm = stafem.Assembler.from_workload(w)
+    asm.set_config(*[cfg[k] for k in ("fused", "rebuild_qd", "rebuild_qo", "stream_qd", "stream_qo", "grid_cap",
+                                      "rebuild_nt")])
+    dfr = [stafem.upload_frame(ids, st) for ids, st in frames]
+
+    def delta_step():
+        for ids, st in dfr:
+            asm.apply_edits_delta(ids, st)
+
+    step_s, _ = graph_time(torch, delta_step, args.steps, args.warmup)
+    n_frames = len(frames) * (args.steps + args.warmup + 2)
+    dr = drift(torch, asm)
+    out = {"workload": "the headline fracture+reinsertion stream under the +/- delta policy",
+           "delta_us_per_frame": round(step_s * 1e6 / len(frames), 3),
+           "exact_us_per_frame": round(exact_step_s * 1e6 / len(frames), 3),
+           "exact_over_delta": round(exact_step_s / step_s, 3),
+           "drift_after_frames": n_frames, "drift": dr}
+    # repeated locality: the peak frame's tets (a slab near the impact point) deleted and
+    # reinserted on alternate frames
+    peak = int(np.argmax([len(f[0]) for f in frames[:24]]))
+    slab = frames[peak][0]
+    off = stafem.upload_frame(slab, np.zeros(len(slab), np.uint8))
+    on = stafem.upload_frame(slab, np.ones(len(slab), np.uint8))
+    cycle = [off, on] * 4
+
+    def exact_loc():
+        for ids, st in cycle:
+            asm.apply_edits(ids, st)
+
+    def delta_loc():
+        for ids, st in cycle:
+            asm.apply_edits_delta(ids, st)
+
+    asm.full_rebuild()
+    ex_s, _ = graph_time(torch, exact_loc, args.steps, args.warmup)
+    de_s, g = graph_time(torch, delta_loc, args.steps, args.warmup)
+    asm.full_rebuild()
+    torch.cuda.synchronize()
+    reps = 125  # 1000 frames
+    for _ in range(reps):
+        g.replay()
+    out["locality"] = {"slab_tets": int(len(slab)), "frames_per_step": len(cycle),
+                       "exact_us_per_frame": round(ex_s * 1e6 / len(cycle), 3),
+                       "delta_us_per_frame": round(de_s * 1e6 / len(cycle), 3),
+                       "exact_over_delta": round(ex_s / de_s, 3),
+                       "drift_after_frames": reps * len(cycle), "drift": drift(torch, asm)}
+    assert asm.status_sync() == stafem.STA_OK
+    asm.close()
+    log(f"[bench] delta: {out['delta_us_per_frame']} us/frame (exact {out['exact_us_per_frame']}), drift "
+        f"{dr['max_abs']:.3e}; locality {out['locality']['delta_us_per_frame']} vs "
+        f"{out['locality']['exact_us_per_frame']} us/frame, drift {out['locality']['drift']['max_abs']:.3e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -443,6 +639,8 @@ def main():
     if not args.quick and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, w, frames, stats)
     if not args.quick and not args.no_extras:
+        out["delta"] = delta_section(torch, stafem, w, frames, out["tuned_config"], step_s, args)
+        out["proxy"] = proxy_section(torch, stafem, w, frames, args)
         r = workloads.make_refinement(args.seed)
         rf = r.frames[:24]
         rframes = rf + [(ids, (1 - st).astype(np.uint8)) for ids, st in reversed(rf)]

@@ -112,6 +112,22 @@ sta_status sta_full_rebuild(sta_ctx* ctx, void* stream);
 sta_status sta_apply_edits(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* states_dev,
                            int64_t n_edits, void* stream);
 
+/* The paper's +/- delta policy for element assembly (Sec. 3.4, Sec. 3.5
+ * streaming_update): each changed tet's local contributions are added to
+ * (activation) or subtracted from (deletion) the touched entries directly,
+ * with FP64 atomics, and nothing is re-summed.  Faster per touched entry
+ * than sta_apply_edits, but the result depends on the order in which
+ * concurrent edits land: it equals the rebuild only up to rounding, and the
+ * difference can grow over many frames (drift).  The mask and per-element
+ * contributions are kept as sta_apply_edits expects, so the exact policy or
+ * sta_full_rebuild may follow at any time (a rebuild removes the drift).
+ * Arguments as sta_apply_edits; if n_dev (device int32) is not NULL the edit
+ * count is *n_dev and n_edits is the arrays' capacity (graph-capturable).
+ * Invalid or duplicate edits are skipped (not rolled back) and reported by
+ * sta_status_sync.  Host errors: STA_EINVAL, STA_ESTALE. */
+sta_status sta_apply_edits_delta(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* states_dev, int64_t n_edits,
+                                 const int32_t* n_dev, void* stream);
+
 /* sta_apply_edits with the edit count read on the device: *n_dev (device
  * int32) edits are taken from ids_dev / states_dev, whose allocations hold
  * `capacity` entries (1 <= capacity <= n_tets).  Nothing on the host depends
@@ -163,6 +179,7 @@ sta_status sta_last_frame_stats(sta_ctx* ctx, void* stream, int64_t* out, int n_
 #define STA_KERNEL_ADJOINT 4
 #define STA_KERNEL_SOLVE 5     /* all kernels of one CG solve */
 #define STA_KERNEL_FRAME 6     /* fused frame: both streaming phases in one launch */
+#define STA_KERNEL_DELTA 7     /* +/- delta frame (sta_apply_edits_delta), both launches */
 #define STA_NUM_KERNELS 8
 sta_status sta_enable_kernel_timing(sta_ctx* ctx, int on);
 sta_status sta_kernel_times(sta_ctx* ctx, void* stream, int64_t* launches, double* ms);

@@ -63,6 +63,9 @@ def lib():
         L.oracle_rebuild.argtypes = [_i64, _d, _i64, _i32, _d, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, _u8, _i32, _i32, _i64, _d]
         L.oracle_rebuild.restype = ctypes.c_int
+        L.oracle_rebuild_weighted.argtypes = [_i64, _d, _i64, _i32, _d, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_double, _d, ctypes.c_int, _i32, _i32, _i64, _d]
+        L.oracle_rebuild_weighted.restype = ctypes.c_int
         L.oracle_dense.argtypes = [_i64, _d, _i64, _i32, _d, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_double, _u8, _d]
         L.oracle_dense.restype = None
@@ -121,6 +124,21 @@ def rebuild(x, tets, E, nu, rho, dt, mask, rowptr, colidx) -> np.ndarray:
                               _p(rowptr, _i32), _p(colidx, _i32), nnz, _p(vals, _d))
     if rc != 0:
         raise RuntimeError(f"oracle_rebuild failed ({rc}): pattern lacks an entry")
+    return vals
+
+
+def rebuild_weighted(x, tets, E, nu, rho, dt, weights, rowptr, colidx, count_only=False) -> np.ndarray:
+    """For error bounds: per CSR entry, the sum over candidates e with weights[e] != 0 of
+    weights[e] * |A_e term| (or of weights[e] alone with count_only)."""
+    x, tets, E, w = _f64(x), _i32a(tets), _f64(E), _f64(weights)
+    rowptr, colidx = _i32a(rowptr), _i32a(colidx)
+    nnz = int(rowptr[-1])
+    vals = np.empty(nnz)
+    rc = lib().oracle_rebuild_weighted(x.shape[0], _p(x, _d), tets.shape[0], _p(tets, _i32), _p(E, _d),
+                                       float(nu), float(rho), float(dt), _p(w, _d), int(bool(count_only)),
+                                       _p(rowptr, _i32), _p(colidx, _i32), nnz, _p(vals, _d))
+    if rc != 0:
+        raise RuntimeError(f"oracle_rebuild_weighted failed ({rc}): pattern lacks an entry")
     return vals
 
 

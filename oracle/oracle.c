@@ -166,6 +166,39 @@ int oracle_rebuild(int64_t n_nodes, const double *x, int64_t n_tets, const int32
     return OR_OK;
 }
 
+/* Weighted magnitude assembly, for error bounds (not part of the method):
+ * values[s] = sum over candidates e with w[e] != 0 of w[e] * |A_e term| at
+ * slot s, or of w[e] alone when count_only (then an entry gets the weighted
+ * number of candidates that reach it).  Same scatter as oracle_rebuild. */
+int oracle_rebuild_weighted(int64_t n_nodes, const double *x, int64_t n_tets, const int32_t *tets,
+                            const double *E, double nu, double rho, double dt, const double *w, int count_only,
+                            const int32_t *rowptr, const int32_t *colidx, int64_t nnz, double *values)
+{
+    (void)n_nodes;
+    for (int64_t s = 0; s < nnz; ++s)
+        values[s] = 0.0;
+    double X[12], A[144];
+    for (int64_t e = 0; e < n_tets; ++e) {
+        if (w[e] == 0.0)
+            continue;
+        const int32_t *t = tets + 4 * e;
+        if (!count_only) {
+            gather_X(x, t, X);
+            oracle_element(X, E[e], nu, rho, dt, A);
+        }
+        for (int r = 0; r < 12; ++r)
+            for (int c = 0; c < 12; ++c) {
+                int64_t row = 3 * (int64_t)t[r / 3] + r % 3;
+                int64_t col = 3 * (int64_t)t[c / 3] + c % 3;
+                int64_t s = find_slot(rowptr, colidx, row, col);
+                if (s < 0)
+                    return OR_ENOSLOT;
+                values[s] = values[s] + (count_only ? w[e] : w[e] * fabs(A[r * 12 + c]));
+            }
+    }
+    return OR_OK;
+}
+
 /* Dense textbook assembly, eq. (8): D (3n x 3n, row-major) := 0; for each
  * active element in ascending id, D += P^T A_e P.  For tiny meshes only. */
 void oracle_dense(int64_t n_nodes, const double *x, int64_t n_tets, const int32_t *tets,

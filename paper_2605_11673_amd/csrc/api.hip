@@ -388,6 +388,24 @@ sta_status sta_apply_edits_dev(sta_ctx* ctx, const int32_t* ids_dev, const uint8
     return run_frame(ctx, ids_dev, states_dev, (int32_t)capacity, n_dev, static_cast<hipStream_t>(stream));
 }
 
+sta_status sta_apply_edits_delta(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* states_dev, int64_t n_edits,
+                                 const int32_t* n_dev, void* stream)
+{
+    if (!ctx)
+        return STA_EINVAL;
+    if (n_edits < 0 || n_edits > ctx->n_tets || (n_dev && n_edits < 1))
+        return fail(ctx, STA_EINVAL, "n_edits must be in [0, n_tets] ([1, n_tets] as a capacity)");
+    if (n_edits > 0 && (!ids_dev || !states_dev))
+        return fail(ctx, STA_EINVAL, "NULL edit array");
+    if (ctx->stale)
+        return fail(ctx, STA_ESTALE, "parameters changed: call sta_full_rebuild before sta_apply_edits_delta");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const hipError_t e = timed(ctx, STA_KERNEL_DELTA, s, [&] {
+        return launch_delta_frame(ctx->v, ids_dev, states_dev, (int32_t)n_edits, n_dev, s);
+    });
+    return e == hipSuccess ? STA_OK : hip_fail(ctx, e, "delta frame");
+}
+
 const double* sta_values_ptr(const sta_ctx* ctx)
 {
     return ctx ? ctx->v.values : nullptr;

@@ -360,38 +360,32 @@ __global__ __launch_bounds__(kBlock) void k_reduce_all(DevView v, int64_t diag_l
 // Streaming update
 // ---------------------------------------------------------------------------
 
-// Write the values of local block (A, B) of tet e (block orientation: row
-// vertex = the one with the smaller node id; same arithmetic as store_element).
-template <int A, int B>
-__device__ __forceinline__ void store_slot_ab(const DevView& v, const Geo& G, const int* id, int pos)
+// Gradient of local vertex a (0..3, not a compile-time constant) by
+// selects, so that no register array is indexed at run time.
+__device__ __forceinline__ void pick_gradient(const Geo& G, int a, double* g)
 {
-    if (A == B) {
-        const double s = dot3(G.g[A], G.g[A]);
-        double2* dst = reinterpret_cast<double2*>(v.cd + 6 * (size_t)pos);
-        dst[0] = make_double2(entry(G.g[A], G.g[A], s, G, 0, 0, true), entry(G.g[A], G.g[A], s, G, 0, 1, true));
-        dst[1] = make_double2(entry(G.g[A], G.g[A], s, G, 0, 2, true), entry(G.g[A], G.g[A], s, G, 1, 1, true));
-        dst[2] = make_double2(entry(G.g[A], G.g[A], s, G, 1, 2, true), entry(G.g[A], G.g[A], s, G, 2, 2, true));
-    } else {
-        const bool sw = id[A] > id[B];
-        double ga[3], gb[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            ga[i] = sw ? G.g[B][i] : G.g[A][i];
-            gb[i] = sw ? G.g[A][i] : G.g[B][i];
-        }
-        const double s = dot3(ga, gb);
-        double* dst = v.co + 9 * (size_t)pos;
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                dst[3 * i + j] = entry(ga, gb, s, G, i, j, false);
-    }
+    for (int i = 0; i < 3; ++i)
+        g[i] = a == 0 ? G.g[0][i] : (a == 1 ? G.g[1][i] : (a == 2 ? G.g[2][i] : G.g[3][i]));
 }
 
-// Write block slot r (0..3 diagonal a=r, 4..9 pairs 01 02 03 12 13 23) of a
-// tet with vertex ids t: its element-matrix values (geometry G) when active,
-// zeros when not.
+__device__ __forceinline__ int tet_vertex(int4 t, int a)
+{
+    return a == 0 ? t.x : (a == 1 ? t.y : (a == 2 ? t.z : t.w));
+}
+
+// Local vertices (A, B) of block slot r: r < 4 diagonal (r, r); 4..9 the
+// pairs 01 02 03 12 13 23.  Two bits per slot, packed.
+constexpr uint32_t kSlotA = 0u | 1u << 2 | 2u << 4 | 3u << 6 | 0u << 8 | 0u << 10 | 0u << 12 | 1u << 14 | 1u << 16 |
+                            2u << 18;
+constexpr uint32_t kSlotB = 0u | 1u << 2 | 2u << 4 | 3u << 6 | 1u << 8 | 2u << 10 | 3u << 12 | 2u << 14 | 3u << 16 |
+                            3u << 18;
+
+// Write block slot r of a tet with vertex ids t: its element-matrix values
+// (geometry G; block orientation: row vertex = the one with the smaller node
+// id; same arithmetic as store_element) when active, zeros when not.  One
+// code path serves all ten slots (the slot only selects gradients), which
+// keeps the streaming kernels' instruction footprint small.
 __device__ __forceinline__ void store_slot(const DevView& v, int4 t, const Geo& G, int r, int pos, bool active)
 {
     if (!active) {
@@ -411,18 +405,28 @@ __device__ __forceinline__ void store_slot(const DevView& v, int4 t, const Geo& 
     }
     if (G.det == 0.0 && r == 0)
         atomicOr(&v.ctl->err, ERR_DEGENERATE);
-    const int id[4] = {t.x, t.y, t.z, t.w};
-    switch (r) {
-    case 0: store_slot_ab<0, 0>(v, G, id, pos); break;
-    case 1: store_slot_ab<1, 1>(v, G, id, pos); break;
-    case 2: store_slot_ab<2, 2>(v, G, id, pos); break;
-    case 3: store_slot_ab<3, 3>(v, G, id, pos); break;
-    case 4: store_slot_ab<0, 1>(v, G, id, pos); break;
-    case 5: store_slot_ab<0, 2>(v, G, id, pos); break;
-    case 6: store_slot_ab<0, 3>(v, G, id, pos); break;
-    case 7: store_slot_ab<1, 2>(v, G, id, pos); break;
-    case 8: store_slot_ab<1, 3>(v, G, id, pos); break;
-    default: store_slot_ab<2, 3>(v, G, id, pos); break;
+    int A = (int)(kSlotA >> (2 * r)) & 3, B = (int)(kSlotB >> (2 * r)) & 3;
+    if (tet_vertex(t, A) > tet_vertex(t, B)) {
+        const int c = A;
+        A = B;
+        B = c;
+    }
+    double ga[3], gb[3];
+    pick_gradient(G, A, ga);
+    pick_gradient(G, B, gb);
+    const double s = dot3(ga, gb);
+    if (r < 4) {
+        double2* dst = reinterpret_cast<double2*>(v.cd + 6 * (size_t)pos);
+        dst[0] = make_double2(entry(ga, ga, s, G, 0, 0, true), entry(ga, ga, s, G, 0, 1, true));
+        dst[1] = make_double2(entry(ga, ga, s, G, 0, 2, true), entry(ga, ga, s, G, 1, 1, true));
+        dst[2] = make_double2(entry(ga, ga, s, G, 1, 2, true), entry(ga, ga, s, G, 2, 2, true));
+    } else {
+        double* dst = v.co + 9 * (size_t)pos;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                dst[3 * i + j] = entry(ga, gb, s, G, i, j, false);
     }
 }
 
@@ -673,6 +677,136 @@ __global__ __launch_bounds__(kBlock) void k_touched(DevView v, const int32_t* __
         touched_lane<QD, QO>(v, d, id, fe, i, r, vi, q);
 }
 
+// ---------------------------------------------------------------------------
+// +/- delta policy (the paper's streaming_update for element assembly:
+// touched entries change by adding or removing the edited elements' local
+// contributions, Sec. 3.4 / Sec. 3.5)
+// ---------------------------------------------------------------------------
+
+// Add s * (block slot r's values) into the CSR values of block d (and its
+// mirror), with hardware FP64 atomics.  The order in which concurrent edits
+// land is not fixed, so the result is reproducible only up to rounding.
+__device__ __forceinline__ void delta_block(const DevView& v, const BlockDesc& d, const double* x, bool add)
+{
+    if (d.kind == 0) {
+#pragma unroll
+        for (int vi = 0; vi < 6; ++vi) {
+            const int p = kDiagP[vi], q = kDiagQ[vi];
+            const double y = add ? x[vi] : -x[vi];
+            unsafeAtomicAdd(v.values + d.up + p * d.rl + q, y);
+            if (p != q)
+                unsafeAtomicAdd(v.values + d.up + q * d.rl + p, y);
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const double y = add ? x[3 * p + q] : -x[3 * p + q];
+                unsafeAtomicAdd(v.values + d.up + p * d.rl + q, y);
+                unsafeAtomicAdd(v.values + d.lo + q * d.rlj + p, y);
+            }
+    }
+}
+
+// Lane r of edit i under the delta policy (16 lanes per edit, lane r < 10
+// owns block slot r).  A changed tet's slot values are added (activation:
+// computed and stored in its slot first) or subtracted (deletion: read from
+// its slot, which is then zeroed), so the per-element contributions stay as
+// the exact policy expects and either policy may follow.  Invalid and
+// duplicate edits are skipped and reported; nothing is rolled back.
+__device__ __forceinline__ int delta_lane(const DevView& v, int id, unsigned st, int r)
+{
+    if (id < 0 || id >= v.n_tets || st > 1u)
+        return r == 0 ? ERR_RANGE : 0;
+    const bool slot = r < 10;
+    uint32_t eb = 0;
+    int ep = 0;
+    if (slot) {
+        eb = (uint32_t)v.e2b[10 * (size_t)id + r];
+        ep = v.e2p[10 * (size_t)id + r];
+    }
+    int4 t = make_int4(0, 0, 0, 0);
+    double E = 0.0;
+    if (slot && st) {
+        t = v.T[id];
+        E = v.E[id];
+    }
+    const uint8_t prev = v.mask[id];
+    unsigned taken = 0u;
+    if (r == 0)
+        taken = atomicExch(&v.estamp[id], 1u);
+    BlockDesc bd = empty_desc();
+    if (slot)
+        bd = load_desc(v.desc + eb);
+    double X[4][3];
+    if (slot && st)
+        load_vertices(v, t, X);
+    const bool owner = __shfl(taken, (threadIdx.x & 63) & ~(kEditLanes - 1), 64) == 0u;
+    if (!owner)
+        return r == 0 ? ERR_DUP : 0;
+    if (prev == st)
+        return 0;
+    if (r == 0)
+        v.mask[id] = (uint8_t)st;
+    if (!slot)
+        return 0;
+    const int nv = r < 4 ? 6 : 9;
+    const double* src = r < 4 ? v.cd + 6 * (size_t)ep : v.co + 9 * (size_t)ep;
+    double x[9];
+    Geo G;
+    if (st) {
+        geometry_from(v, X, E, G);
+        store_slot(v, t, G, r, ep, true);
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+        x[k] = k < nv ? src[k] : 0.0;
+    if (!st)
+        store_slot(v, t, G, r, ep, false);
+    delta_block(v, bd, x, st != 0u);
+    return 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_delta_edits(DevView v, const int32_t* __restrict__ ids,
+                                                        const uint8_t* __restrict__ states, int32_t n_host,
+                                                        const int32_t* __restrict__ n_dev)
+{
+    const int gt = blockIdx.x * kBlock + threadIdx.x;
+    const int i = gt / kEditLanes;
+    int id = -1;
+    unsigned st = 0;
+    if (i < n_host) {
+        id = ids[i];
+        st = states[i];
+    }
+    bool bad_n;
+    const int n = frame_count(n_host, n_dev, bad_n);
+    int bits = (bad_n && gt == 0) ? ERR_RANGE : 0;
+    if (i < n)
+        bits |= delta_lane(v, id, st, gt - i * kEditLanes);
+    if (bits)
+        atomicOr(&v.ctl->err, bits);
+    if (gt == 0) {
+        v.ctl->last_n = n;
+        v.ctl->frame_err = 0;
+    }
+}
+
+// Release the frame's tet stamps (one lane per edit).
+__global__ __launch_bounds__(kBlock) void k_delta_clear(DevView v, const int32_t* __restrict__ ids, int32_t n_host,
+                                                        const int32_t* __restrict__ n_dev)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    bool bad_n;
+    const int n = frame_count(n_host, n_dev, bad_n);
+    if (i < n) {
+        const int id = ids[i];
+        if (id >= 0 && id < v.n_tets)
+            v.estamp[id] = 0u;
+    }
+}
+
 // Grid-wide barrier for a co-resident grid (the host sizes the grid from the
 // occupancy so that every workgroup is resident).  The spin is bounded: a
 // grid that is not co-resident reports ERR_TIMEOUT instead of hanging.
@@ -805,6 +939,18 @@ hipError_t launch_edit_phase(const DevView& v, const int32_t* ids, const uint8_t
     // an empty list still runs one workgroup of each phase: they record the frame (count 0)
     hipLaunchKernelGGL(k_edits, dim3(n_host > 0 ? blocks_for((int64_t)n_host * kEditLanes) : 1u), dim3(kBlock), 0,
                        s, v, ids, states, n_host, n_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_delta_frame(const DevView& v, const int32_t* ids, const uint8_t* states, int32_t n_host,
+                              const int32_t* n_dev, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_delta_edits, dim3(n_host > 0 ? blocks_for((int64_t)n_host * kEditLanes) : 1u), dim3(kBlock),
+                       0, s, v, ids, states, n_host, n_dev);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n_host == 0)
+        return e;
+    hipLaunchKernelGGL(k_delta_clear, dim3(blocks_for(n_host)), dim3(kBlock), 0, s, v, ids, n_host, n_dev);
     return hipGetLastError();
 }
 

@@ -156,6 +156,10 @@ hipError_t launch_edit_phase(const DevView& v, const int32_t* ids, const uint8_t
                              const int32_t* n_dev, hipStream_t s);
 hipError_t launch_touched_phase(const DevView& v, const MapConfig& m, const int32_t* ids, int32_t n_host,
                                 const int32_t* n_dev, hipStream_t s);
+// +/- delta policy: one launch applying the edits' contributions with FP64
+// atomics, one releasing the tet stamps.
+hipError_t launch_delta_frame(const DevView& v, const int32_t* ids, const uint8_t* states, int32_t n_host,
+                              const int32_t* n_dev, hipStream_t s);
 // Fused frame: both phases in one persistent launch of `grid` co-resident workgroups.
 hipError_t frame_max_grid(const MapConfig& m, int device, int* max_grid);
 int frame_grid_for(const MapConfig& m, int32_t n_host, int max_grid, int grid_cap);

@@ -45,6 +45,7 @@ SIGNATURES = {
     "sta_full_rebuild": (_int, [_vp, _vp]),
     "sta_apply_edits": (_int, [_vp, _vp, _vp, _i64, _vp]),
     "sta_apply_edits_dev": (_int, [_vp, _vp, _vp, _vp, _i64, _vp]),
+    "sta_apply_edits_delta": (_int, [_vp, _vp, _vp, _i64, _vp, _vp]),
     "sta_values_ptr": (_vp, [_vp]),
     "sta_copy_values": (_int, [_vp, _vp, _vp]),
     "sta_sizes": (_int, [_vp, _i64p, _i64p, _i64p, _i64p]),
@@ -193,6 +194,16 @@ class Assembler:
         _check(load().sta_apply_edits_dev(self._ctx, _dev_ptr(ids), _dev_ptr(states), _dev_ptr(n_dev),
                                           int(ids.numel()), _stream_handle(stream)), self._ctx)
 
+    def apply_edits_delta(self, ids: torch.Tensor, states: torch.Tensor, n_dev: torch.Tensor | None = None,
+                          stream=None):
+        """The +/- delta policy (sta_apply_edits_delta): exact only up to rounding."""
+        if ids.dtype != torch.int32 or states.dtype != torch.uint8 or ids.numel() != states.numel() \
+                or not (ids.is_cuda and states.is_cuda) or (n_dev is not None and n_dev.dtype != torch.int32):
+            raise TypeError("ids int32 and states uint8 CUDA tensors of equal length (n_dev int32)")
+        nd = _vp(0) if n_dev is None else _dev_ptr(n_dev)
+        _check(load().sta_apply_edits_delta(self._ctx, _dev_ptr(ids), _dev_ptr(states), int(ids.numel()), nd,
+                                            _stream_handle(stream)), self._ctx)
+
     def values_ptr(self) -> int:
         return int(load().sta_values_ptr(self._ctx) or 0)
 
@@ -225,7 +236,7 @@ class Assembler:
         d["touched_incidences"] = d["diag_incidences"] + d["off_incidences"]
         return d
 
-    KERNELS = ("element", "reduce", "edits", "touched", "adjoint", "solve", "frame", "spare")
+    KERNELS = ("element", "reduce", "edits", "touched", "adjoint", "solve", "frame", "delta")
 
     def enable_kernel_timing(self, on: bool = True):
         _check(load().sta_enable_kernel_timing(self._ctx, 1 if on else 0), self._ctx)

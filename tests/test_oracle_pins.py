@@ -404,3 +404,29 @@ def test_gradient_exact_difference_fd():
             xm[i, k] -= h
             fd = local_diff(ring, xp, xm, w.E, w.E)
             assert abs(fd - gx[i, k]) <= 1e-6 * np.abs(gx[i]).max()
+
+
+def test_weighted_magnitude_assembly():
+    """The error-bound helper: with unit weights on the active tets its diagonal equals the
+    rebuild's (diagonal terms are non-negative, same order), every entry bounds the
+    rebuild's magnitude, and count_only gives each entry its number of active incident
+    tets (counted here from the node pairs directly)."""
+    import oracle
+    w = W.make_fracture(seed=4, n=5, counts=[20])
+    rowptr, colidx = oracle.pattern(w.n_nodes, w.tets)
+    mask = w.mask_after(0)
+    vals = oracle.rebuild(w.x, w.tets, w.E, w.nu, w.rho, w.dt, mask, rowptr, colidx)
+    mag = oracle.rebuild_weighted(w.x, w.tets, w.E, w.nu, w.rho, w.dt, mask.astype(float), rowptr, colidx)
+    cnt = oracle.rebuild_weighted(w.x, w.tets, w.E, w.nu, w.rho, w.dt, mask.astype(float), rowptr, colidx,
+                                  count_only=True)
+    rows = np.repeat(np.arange(3 * w.n_nodes), np.diff(rowptr))
+    diag = rows == colidx
+    assert np.array_equal(vals[diag].view(np.uint64), mag[diag].view(np.uint64))
+    assert np.all(mag >= np.abs(vals))
+    pairs = {}
+    for t in w.tets[mask.astype(bool)]:
+        for a in t:
+            for b in t:
+                pairs[(int(a), int(b))] = pairs.get((int(a), int(b)), 0) + 1
+    want = np.array([pairs.get((int(r) // 3, int(c) // 3), 0) for r, c in zip(rows, colidx)], dtype=float)
+    assert np.array_equal(cnt, want)
