@@ -168,7 +168,10 @@ sta_status sta_pattern_host(const sta_ctx* ctx, int32_t* rowptr, int32_t* colidx
 sta_status sta_last_frame_stats(sta_ctx* ctx, void* stream, int64_t* out, int n_out);
 
 /* Per-kernel timing (tracing aid).  While enabled, every kernel this context
- * launches is bracketed by two HIP events on the launch stream.
+ * launches is timed by two HIP events on the launch stream: attached to the
+ * dispatch itself for the single-kernel ids (element, reduce, edits,
+ * touched, frame: the kernel's execution time, as a profiler reports it),
+ * recorded around the launches for the others (adjoint, solve, delta).
  * sta_kernel_times synchronises `stream`, writes per kernel id the number of
  * launches and their summed event-to-event duration in milliseconds (arrays
  * of STA_NUM_KERNELS), and resets the counters. */

@@ -93,20 +93,39 @@ hipEvent_t take_event(sta_ctx* c)
     return ev;
 }
 
-// Run one launcher, bracketed by events when kernel timing is on.
+// Run one launcher with kernel timing when it is on.  A launcher of a single
+// kernel (single = true) gets the events attached to the dispatch, so they
+// time the kernel alone; other launchers are bracketed by event records
+// (which adds the launch gaps between their kernels).
 template <class F>
-hipError_t timed(sta_ctx* c, int kernel, hipStream_t s, F&& launch)
+hipError_t timed(sta_ctx* c, int kernel, hipStream_t s, F&& launch, bool single = false)
 {
     if (!c->timing)
         return launch();
     hipEvent_t a = take_event(c), b = take_event(c);
     if (!a || !b)
         return hipErrorOutOfMemory;
-    hipError_t e = hipEventRecord(a, s);
-    if (e == hipSuccess)
+    hipError_t e = hipSuccess;
+    if (single) {
+        KernelEvents& ev = kernel_events();
+        ev.start = a;
+        ev.stop = b;
+        ev.used = false;
         e = launch();
-    if (e == hipSuccess)
-        e = hipEventRecord(b, s);
+        const bool used = ev.used;
+        ev = KernelEvents{};
+        if (!used) {  // nothing was launched: nothing to time
+            c->event_pool.push_back(a);
+            c->event_pool.push_back(b);
+            return e;
+        }
+    } else {
+        e = hipEventRecord(a, s);
+        if (e == hipSuccess)
+            e = launch();
+        if (e == hipSuccess)
+            e = hipEventRecord(b, s);
+    }
     c->timed.push_back({kernel, a, b});
     return e;
 }
@@ -114,6 +133,12 @@ hipError_t timed(sta_ctx* c, int kernel, hipStream_t s, F&& launch)
 }  // namespace
 
 namespace sta {
+
+KernelEvents& kernel_events()
+{
+    thread_local KernelEvents ev;
+    return ev;
+}
 
 std::string& build_error()
 {
@@ -315,14 +340,17 @@ sta_status run_frame(sta_ctx* ctx, const int32_t* ids, const uint8_t* states, in
                 return fail(ctx, STA_EINVAL, "fused frame kernel cannot be resident");
         }
         const int grid = frame_grid_for(ctx->stream_map, n_host, ctx->frame_max_grid, ctx->frame_grid_cap);
-        e = timed(ctx, STA_KERNEL_FRAME, s,
-                  [&] { return launch_frame(ctx->v, ctx->stream_map, grid, ids, states, n_host, n_dev, s); });
+        e = timed(
+            ctx, STA_KERNEL_FRAME, s,
+            [&] { return launch_frame(ctx->v, ctx->stream_map, grid, ids, states, n_host, n_dev, s); }, true);
     } else {
-        e = timed(ctx, STA_KERNEL_EDITS, s,
-                  [&] { return launch_edit_phase(ctx->v, ids, states, n_host, n_dev, s); });
+        e = timed(
+            ctx, STA_KERNEL_EDITS, s, [&] { return launch_edit_phase(ctx->v, ids, states, n_host, n_dev, s); },
+            true);
         if (e == hipSuccess)
-            e = timed(ctx, STA_KERNEL_TOUCHED, s,
-                      [&] { return launch_touched_phase(ctx->v, ctx->stream_map, ids, n_host, n_dev, s); });
+            e = timed(
+                ctx, STA_KERNEL_TOUCHED, s,
+                [&] { return launch_touched_phase(ctx->v, ctx->stream_map, ids, n_host, n_dev, s); }, true);
     }
     if (e != hipSuccess)
         return hip_fail(ctx, e, "frame launch");
@@ -351,9 +379,11 @@ sta_status sta_full_rebuild(sta_ctx* ctx, void* stream)
     if (!ctx)
         return STA_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = timed(ctx, STA_KERNEL_ELEMENT, s, [&] { return launch_element(ctx->v, ctx->rebuild_map.nt != 0, s); });
+    hipError_t e = timed(
+        ctx, STA_KERNEL_ELEMENT, s, [&] { return launch_element(ctx->v, ctx->rebuild_map.nt != 0, s); }, true);
     if (e == hipSuccess)
-        e = timed(ctx, STA_KERNEL_REDUCE, s, [&] { return launch_reduce_all(ctx->v, ctx->rebuild_map, s); });
+        e = timed(
+            ctx, STA_KERNEL_REDUCE, s, [&] { return launch_reduce_all(ctx->v, ctx->rebuild_map, s); }, true);
     if (e != hipSuccess)
         return hip_fail(ctx, e, "full_rebuild launch");
     ctx->stale = false;

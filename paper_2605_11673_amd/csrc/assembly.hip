@@ -904,9 +904,9 @@ hipError_t launch_element(const DevView& v, bool nt, hipStream_t s)
     if (v.n_tets == 0)
         return hipSuccess;
     if (nt)
-        hipLaunchKernelGGL(k_element<true>, dim3(blocks_for(v.n_tets)), dim3(kBlock), 0, s, v);
+        launch_kernel(&k_element<true>, dim3(blocks_for(v.n_tets)), dim3(kBlock), 0, s, v);
     else
-        hipLaunchKernelGGL(k_element<false>, dim3(blocks_for(v.n_tets)), dim3(kBlock), 0, s, v);
+        launch_kernel(&k_element<false>, dim3(blocks_for(v.n_tets)), dim3(kBlock), 0, s, v);
     return hipGetLastError();
 }
 
@@ -921,10 +921,10 @@ hipError_t launch_reduce_all(const DevView& v, const MapConfig& m, hipStream_t s
 #define LAUNCH(QD, QO)                                                                                    \
     if (m.qd == QD && m.qo == QO) {                                                                       \
         if (m.nt)                                                                                         \
-            hipLaunchKernelGGL((k_reduce_all<QD, QO, true>), dim3(blocks_for(threads)), dim3(kBlock), 0, s, v, \
+            launch_kernel(&k_reduce_all<QD, QO, true>, dim3(blocks_for(threads)), dim3(kBlock), 0, s, v, \
                                diag_lanes);                                                               \
         else                                                                                              \
-            hipLaunchKernelGGL((k_reduce_all<QD, QO, false>), dim3(blocks_for(threads)), dim3(kBlock), 0, s, v, \
+            launch_kernel(&k_reduce_all<QD, QO, false>, dim3(blocks_for(threads)), dim3(kBlock), 0, s, v, \
                                diag_lanes);                                                               \
         return hipGetLastError();                                                                         \
     }
@@ -937,7 +937,7 @@ hipError_t launch_edit_phase(const DevView& v, const int32_t* ids, const uint8_t
                              const int32_t* n_dev, hipStream_t s)
 {
     // an empty list still runs one workgroup of each phase: they record the frame (count 0)
-    hipLaunchKernelGGL(k_edits, dim3(n_host > 0 ? blocks_for((int64_t)n_host * kEditLanes) : 1u), dim3(kBlock), 0,
+    launch_kernel(&k_edits, dim3(n_host > 0 ? blocks_for((int64_t)n_host * kEditLanes) : 1u), dim3(kBlock), 0,
                        s, v, ids, states, n_host, n_dev);
     return hipGetLastError();
 }
@@ -960,7 +960,7 @@ hipError_t launch_touched_phase(const DevView& v, const MapConfig& m, const int3
 #define LAUNCH(QD, QO)                                                                                      \
     if (m.qd == QD && m.qo == QO) {                                                                         \
         const int64_t lanes = (int64_t)n_host * Phase2<QD, QO>::kLanes;                                     \
-        hipLaunchKernelGGL((k_touched<QD, QO>), dim3(n_host > 0 ? blocks_for(lanes) : 1u), dim3(kBlock), 0, s, v, \
+        launch_kernel(&k_touched<QD, QO>, dim3(n_host > 0 ? blocks_for(lanes) : 1u), dim3(kBlock), 0, s, v, \
                            ids, n_host, n_dev);                                                             \
         return hipGetLastError();                                                                           \
     }
@@ -1006,7 +1006,7 @@ hipError_t launch_frame(const DevView& v, const MapConfig& m, int grid, const in
 {
 #define LAUNCH(QD, QO)                                                                                        \
     if (m.qd == QD && m.qo == QO) {                                                                           \
-        hipLaunchKernelGGL((k_frame<QD, QO>), dim3(grid), dim3(kBlock), 0, s, v, ids, states, n_host, n_dev); \
+        launch_kernel(&k_frame<QD, QO>, dim3(grid), dim3(kBlock), 0, s, v, ids, states, n_host, n_dev); \
         return hipGetLastError();                                                                             \
     }
     STA_MAPPINGS(LAUNCH)

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "stafem.h"
+#include <hip/hip_ext.h>
 
 namespace sta {
 
@@ -146,6 +147,27 @@ struct sta_ctx {
 };
 
 namespace sta {
+
+// Per-kernel timing: while start is set, launch_kernel attaches the two
+// events to the dispatch itself (hipExtLaunchKernel), so their interval is
+// the kernel's execution, as a profiler reports it.  Thread-local.
+struct KernelEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool used = false;
+};
+KernelEvents& kernel_events();
+
+template <typename... KArgs, typename... Args>
+inline void launch_kernel(void (*k)(KArgs...), dim3 grid, dim3 block, uint32_t shmem, hipStream_t s, Args... args)
+{
+    KernelEvents& ev = kernel_events();
+    if (ev.start) {
+        ev.used = true;
+        hipExtLaunchKernelGGL(k, grid, block, shmem, s, ev.start, ev.stop, 0u, static_cast<KArgs>(args)...);
+    } else {
+        hipLaunchKernelGGL(k, grid, block, shmem, s, static_cast<KArgs>(args)...);
+    }
+}
 
 // Kernel launchers (assembly.hip).
 hipError_t launch_element(const DevView& v, bool nt, hipStream_t s);
