@@ -66,6 +66,8 @@ def lib():
         L.oracle_rebuild_weighted.argtypes = [_i64, _d, _i64, _i32, _d, ctypes.c_double, ctypes.c_double,
                                               ctypes.c_double, _d, ctypes.c_int, _i32, _i32, _i64, _d]
         L.oracle_rebuild_weighted.restype = ctypes.c_int
+        L.oracle_lumped_mass.argtypes = [_i64, _d, _i64, _i32, ctypes.c_double, _u8, _d]
+        L.oracle_lumped_mass.restype = None
         L.oracle_dense.argtypes = [_i64, _d, _i64, _i32, _d, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_double, _u8, _d]
         L.oracle_dense.restype = None
@@ -195,6 +197,24 @@ def pcg(rowptr, colidx, vals, b, rtol=1e-12, max_iter=20000):
     if rc != 0:
         raise RuntimeError(f"oracle_pcg failed ({rc})")
     return x, int(it.value), float(rr.value)
+
+
+def lumped_mass(x, tets, rho, mask) -> np.ndarray:
+    """M_t per dof (3 per node): active tets' rho V / 4, summed in ascending tet id."""
+    x, tets, mask = _f64(x), _i32a(tets), _u8a(mask)
+    m = np.empty(3 * x.shape[0])
+    lib().oracle_lumped_mass(x.shape[0], _p(x, _d), tets.shape[0], _p(tets, _i32), float(rho), _p(mask, _u8),
+                             _p(m, _d))
+    return m
+
+
+def euler_step(rowptr, colidx, vals, m, u, v, f, h, rtol=1e-12, max_iter=20000):
+    """One implicit-Euler step (Sec. 6.2 eq. (9)): solve (M_t + h^2 K_t) u' = M_t (u + h v) + h^2 f
+    with the oracle PCG (vals = the CSR values of M_t + h^2 K_t, m = M_t per dof), then
+    v' = (u' - u) / h.  Returns (u', v', iters, relres)."""
+    b = m * (u + h * v) + (h * h) * f
+    u1, it, rr = pcg(rowptr, colidx, vals, b, rtol=rtol, max_iter=max_iter)
+    return u1, (u1 - u) / h, it, rr
 
 
 def rebuild_workload(w, mask=None, pat=None):

@@ -199,6 +199,29 @@ int oracle_rebuild_weighted(int64_t n_nodes, const double *x, int64_t n_tets, co
     return OR_OK;
 }
 
+/* Lumped mass of the active set (Sec. 6.2: the maintained M_t of eq. (9)):
+ * m[3i+k] = sum over active tets e containing node i, in ascending e, from
+ * +0.0, of (rho * V_e) * 0.25 with V_e = |det| / 6 (the mass term of the
+ * element formula). */
+void oracle_lumped_mass(int64_t n_nodes, const double *x, int64_t n_tets, const int32_t *tets, double rho,
+                        const uint8_t *mask, double *m)
+{
+    for (int64_t s = 0; s < 3 * n_nodes; ++s)
+        m[s] = 0.0;
+    double X[12];
+    for (int64_t e = 0; e < n_tets; ++e) {
+        if (!mask[e])
+            continue;
+        const int32_t *t = tets + 4 * e;
+        gather_X(x, t, X);
+        const double V = fabs(oracle_det(X)) / 6.0;
+        const double me = (rho * V) * 0.25;
+        for (int a = 0; a < 4; ++a)
+            for (int k = 0; k < 3; ++k)
+                m[3 * (int64_t)t[a] + k] = m[3 * (int64_t)t[a] + k] + me;
+    }
+}
+
 /* Dense textbook assembly, eq. (8): D (3n x 3n, row-major) := 0; for each
  * active element in ascending id, D += P^T A_e P.  For tiny meshes only. */
 void oracle_dense(int64_t n_nodes, const double *x, int64_t n_tets, const int32_t *tets,

@@ -8,6 +8,7 @@ tetrahedron elasticity matrix, the lumped mass of Sec. 6.2 eq. (9), and the
 rebuild invariant of Sec. 3.3.
 """
 from fractions import Fraction as F
+import math
 
 import numpy as np
 import pytest
@@ -430,3 +431,49 @@ def test_weighted_magnitude_assembly():
                 pairs[(int(a), int(b))] = pairs.get((int(a), int(b)), 0) + 1
     want = np.array([pairs.get((int(r) // 3, int(c) // 3), 0) for r, c in zip(rows, colidx)], dtype=float)
     assert np.array_equal(cnt, want)
+
+
+def test_lumped_mass_pins():
+    """M_t equals the diagonal of the rebuild with E = 0 bit for bit (then A = M: the
+    stiffness terms vanish and the element diagonal is exactly its mass term, summed in
+    the same order); on the unjittered fully active cube the total mass is rho x volume 1
+    (to rounding: each tet's volume h^3/6 is rounded once); a node's three dofs agree."""
+    import oracle
+    w = W.make_fracture(seed=6, n=6, counts=[60])
+    mask = w.mask_after(0)
+    m = oracle.lumped_mass(w.x, w.tets, w.rho, mask)
+    rowptr, colidx = oracle.pattern(w.n_nodes, w.tets)
+    vals = oracle.rebuild(w.x, w.tets, np.zeros(w.n_tets), w.nu, w.rho, w.dt, mask, rowptr, colidx)
+    rows = np.repeat(np.arange(3 * w.n_nodes), np.diff(rowptr))
+    diag = np.zeros(3 * w.n_nodes)
+    diag[rows[rows == colidx]] = vals[rows == colidx]
+    assert np.array_equal(m.view(np.uint64), diag.view(np.uint64))
+    assert np.array_equal(m[0::3], m[1::3]) and np.array_equal(m[0::3], m[2::3])
+    c = W.make_cube(0, n=4)
+    mc = oracle.lumped_mass(c.x, c.tets, c.rho, c.mask0)
+    assert abs(math.fsum(mc[0::3]) - c.rho) <= 1e-12 * c.rho
+
+
+def test_euler_step_solves_equation():
+    """One implicit-Euler step from rest under gravity: the returned u' satisfies
+    (M + h^2 K) u' = M (u + h v) + h^2 f to the solver tolerance (checked with scipy's
+    direct solve, a different route), and v' = (u' - u) / h."""
+    import oracle
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    w = W.make_fracture(seed=7, n=4, counts=[10])
+    mask = w.mask_after(0)
+    rowptr, colidx = oracle.pattern(w.n_nodes, w.tets)
+    vals = oracle.rebuild(w.x, w.tets, w.E, w.nu, w.rho, w.dt, mask, rowptr, colidx)
+    m = oracle.lumped_mass(w.x, w.tets, w.rho, mask)
+    f = W.loads_for(w, mask).reshape(-1)
+    u = np.zeros_like(m)
+    v = np.zeros_like(m)
+    u1, v1, it, rr = oracle.euler_step(rowptr, colidx, vals, m, u, v, f, w.dt)
+    A = sp.csr_matrix((vals, colidx, rowptr), shape=(len(m), len(m)))
+    act = A.diagonal() != 0
+    b = m * (u + w.dt * v) + w.dt ** 2 * f
+    ref = np.zeros_like(m)
+    ref[act] = spla.spsolve(A[act][:, act].tocsc(), b[act])
+    assert np.linalg.norm(u1 - ref) <= 1e-9 * np.linalg.norm(ref)
+    assert np.array_equal(v1, (u1 - u) / w.dt) and rr <= 1e-12
