@@ -553,6 +553,58 @@ def delta_section(torch, stafem, w, frames, cfg, exact_step_s, args):
     return out
 
 
+def euler_section(torch, stafem, workloads, w, frames, cfg, args, rtol=1e-8):
+    """Implicit-Euler loop of eq. (9) over the headline stream (one time step per frame,
+    gravity plus a surface load, from rest): each policy's matrix update and the solve,
+    timed per frame; the two policies' trajectories must agree bit for bit."""
+    keys = ("fused", "rebuild_qd", "rebuild_qo", "stream_qd", "stream_qo", "grid_cap", "rebuild_nt")
+    f = torch.from_numpy(workloads.loads_for(w, w.mask0).reshape(-1)).cuda()
+    dfr = [stafem.upload_frame(ids, st) for ids, st in frames]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    res = {}
+    traj = {}
+    for policy in ("stream", "rebuild"):
+        asm = stafem.Assembler.from_workload(w)
+        asm.set_config(*[cfg[k] for k in keys])
+        u = torch.zeros(asm.n_rows, dtype=torch.float64, device="cuda")
+        v = torch.zeros_like(u)
+        upd, sol, its = [], [], []
+        for ids, st in dfr:
+            torch.cuda.synchronize()
+            torch.cuda._sleep(200000)
+            ev[0].record()
+            asm.apply_edits(ids, st)
+            if policy == "rebuild":
+                asm.full_rebuild()
+            ev[1].record()
+            it, _ = asm.euler_step(u, v, f, rtol=rtol)
+            ev[2].record()
+            ev[2].synchronize()
+            upd.append(ev[0].elapsed_time(ev[1]) * 1e3)
+            sol.append(ev[1].elapsed_time(ev[2]) * 1e3)
+            its.append(it)
+        torch.cuda.synchronize()
+        traj[policy] = (u.clone(), v.clone())
+        assert asm.status_sync() == stafem.STA_OK
+        asm.close()
+        res[policy] = {"update_us_mean": round(float(np.mean(upd)), 3),
+                       "solve_us_mean": round(float(np.mean(sol)), 3),
+                       "frame_us_mean": round(float(np.mean(np.add(upd, sol))), 3),
+                       "cg_iterations_mean": round(float(np.mean(its)), 2)}
+    same = all(torch.equal(a.view(torch.int64), b.view(torch.int64)) for a, b in zip(traj["stream"], traj["rebuild"]))
+    out = {"workload": "implicit Euler (M_t + h^2 K_t) u' = M_t (u + h v) + h^2 f, h = dt = 1e-2, one step per frame "
+                       f"of the headline stream, Jacobi-PCG to relative residual {rtol:g}, gravity + surface load",
+           "policies": res,
+           "frame_speedup_stream_vs_rebuild": round(res["rebuild"]["frame_us_mean"] / res["stream"]["frame_us_mean"], 3),
+           "update_speedup_stream_vs_rebuild": round(res["rebuild"]["update_us_mean"] / res["stream"]["update_us_mean"],
+                                                     2),
+           "trajectories_bitwise_equal": bool(same)}
+    log(f"[bench] euler: stream frame {res['stream']['frame_us_mean']} us (update {res['stream']['update_us_mean']}), "
+        f"rebuild frame {res['rebuild']['frame_us_mean']} us (update {res['rebuild']['update_us_mean']}), "
+        f"CG {res['stream']['cg_iterations_mean']} it, same trajectory {same}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -641,6 +693,7 @@ def main():
     if not args.quick and not args.no_extras:
         out["delta"] = delta_section(torch, stafem, w, frames, out["tuned_config"], step_s, args)
         out["proxy"] = proxy_section(torch, stafem, w, frames, args)
+        out["euler"] = euler_section(torch, stafem, workloads, w, frames, out["tuned_config"], args)
         r = workloads.make_refinement(args.seed)
         rf = r.frames[:24]
         rframes = rf + [(ids, (1 - st).astype(np.uint8)) for ids, st in reversed(rf)]

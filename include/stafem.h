@@ -218,6 +218,25 @@ sta_status sta_slot_outer(sta_ctx* ctx, const double* a_dev, const double* b_dev
 sta_status sta_cg_solve(sta_ctx* ctx, const double* values_dev, const double* b_dev, double* x_dev, double rtol,
                         int max_iter, void* stream, int* iters_out, double* relres_out);
 
+/* Lumped mass M_t of the current mask (the maintained mass of Sec. 6.2
+ * eq. (9)): m_dev[3i+k] (device, n_rows) = sum over the active tets of node
+ * i, in ascending tet id from +0.0, of (rho V) / 4, V = |det| / 6 as in the
+ * element formula; equal bit for bit to the diagonal of A_t when E = 0.
+ * Asynchronous. */
+sta_status sta_lumped_mass(sta_ctx* ctx, double* m_dev, void* stream);
+
+/* One implicit-Euler step (Sec. 6.2 eq. (9)) with h = the context's dt and
+ * the current A_t = M_t + h^2 K_t:
+ *   solve A_t u' = M_t (u + h v) + h^2 f by Jacobi-PCG (as sta_cg_solve,
+ *   from u' = 0, relative residual rtol, at most max_iter iterations),
+ *   then v := (u' - u) / h and u := u'.
+ * u_dev, v_dev (device, n_rows, updated in place), f_dev (device, n_rows,
+ * a fixed external load).  Dofs of nodes with no active tet get u' = 0.
+ * Synchronises `stream` (the solver checks convergence on the host).
+ * Errors: STA_EINVAL, STA_ESTALE, STA_ENOMEM, STA_EHIP. */
+sta_status sta_euler_step(sta_ctx* ctx, double* u_dev, double* v_dev, const double* f_dev, double rtol,
+                          int max_iter, void* stream, int* iters_out, double* relres_out);
+
 /* Execution configuration.
  *   fused       0: a frame is two launches (edit phase, touched phase);
  *               1: one persistent launch (both phases, grid barrier between).

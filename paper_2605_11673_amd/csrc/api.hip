@@ -235,6 +235,7 @@ sta_status build_context(const double* x, int64_t n_nodes, const int32_t* tets, 
     ALLOC(undo, n_tets);
     ALLOC(wg_err, 16 * n_tets / 256 + 4096);
     ALLOC(ctl, 1);
+    ALLOC(c->dinc, 4 * n_tets);
 #undef ALLOC
     if (e != hipSuccess) {
         free_all(c);
@@ -273,6 +274,7 @@ sta_status build_context(const double* x, int64_t n_nodes, const int32_t* tets, 
     if (e == hipSuccess) e = upload(ndiag, P.ndiag.data(), P.ndiag.size(), s);
     if (e == hipSuccess) e = upload(e2b, he2b.data(), he2b.size(), s);
     if (e == hipSuccess) e = upload(e2p, P.e2p.data(), P.e2p.size(), s);
+    if (e == hipSuccess) e = upload(c->dinc, P.dinc.data(), P.dinc.size(), s);
     if (e == hipSuccess && n_tets > 0) e = hipMemsetAsync(estamp, 0, sizeof(uint32_t) * n_tets, s);
     if (e == hipSuccess && nb > 0) e = hipMemsetAsync(bstamp, 0, sizeof(uint32_t) * nb, s);
     if (e == hipSuccess && P.nnz > 0) e = hipMemsetAsync(values, 0, sizeof(double) * P.nnz, s);
@@ -584,6 +586,7 @@ sta_status sta_set_params(sta_ctx* ctx, const double* x_dev, const double* E_dev
     if (e != hipSuccess)
         return hip_fail(ctx, e, "set_params launch");
     ctx->stale = true;
+    ctx->tet_ml_stale = true;
     return STA_OK;
 }
 

@@ -133,6 +133,10 @@ struct sta_ctx {
     sta::CgScalars* cg_s = nullptr;
     sta::CgScalars* cg_host = nullptr;  // pinned
     double* adj_xbar = nullptr;     // 3 doubles per diagonal incidence
+    int32_t* dinc = nullptr;        // per diagonal incidence: its tet (segments in ascending tet id)
+    double* tet_ml = nullptr;       // per tet: lumped mass per vertex dof, (rho V) / 4
+    bool tet_ml_stale = true;
+    double* euler_ws = nullptr;     // implicit Euler: M_t, right-hand side, new u (3 x n_rows)
     // batch layout: per mesh node / tet / value offsets (k+1 entries)
     std::vector<int64_t> node_off, tet_off, nnz_off;
     std::string errmsg;
@@ -200,6 +204,13 @@ int cg_partials(int n);
 hipError_t launch_cg_init(const CgView& c, const double* b, double rtol, hipStream_t s);
 hipError_t launch_cg_iterations(const CgView& c, int count, int max_iter, hipStream_t s);
 hipError_t launch_cg_output(const CgView& c, double* x, hipStream_t s);
+
+// Lumped mass and implicit Euler (euler.hip).
+hipError_t launch_tet_mass(const DevView& v, double* tet_ml, hipStream_t s);
+hipError_t launch_lumped_mass(const DevView& v, const int32_t* dinc, const double* tet_ml, double* m, hipStream_t s);
+hipError_t launch_euler_rhs(int n, const double* m, const double* u, const double* v, const double* f, double h,
+                            double* b, hipStream_t s);
+hipError_t launch_euler_update(int n, const double* u1, double* u, double* v, double h, hipStream_t s);
 
 // Context construction shared by single and batched builds (api.hip).
 sta_status build_context(const double* x, int64_t n_nodes, const int32_t* tets, int64_t n_tets, const double* E,

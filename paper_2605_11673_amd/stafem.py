@@ -58,6 +58,8 @@ SIGNATURES = {
     "sta_adjoint": (_int, [_vp, _vp, _vp, _vp, _vp]),
     "sta_slot_outer": (_int, [_vp, _vp, _vp, _dbl, _vp, _vp]),
     "sta_cg_solve": (_int, [_vp, _vp, _vp, _vp, _dbl, _int, _vp, ctypes.POINTER(_int), ctypes.POINTER(_dbl)]),
+    "sta_lumped_mass": (_int, [_vp, _vp, _vp]),
+    "sta_euler_step": (_int, [_vp, _vp, _vp, _vp, _dbl, _int, _vp, ctypes.POINTER(_int), ctypes.POINTER(_dbl)]),
     "sta_set_config": (_int, [_vp, _int, _int, _int, _int, _int, _int, _int]),
     "sta_get_config": (_int, [_vp, ctypes.POINTER(_int)]),
     "sta_autotune": (_int, [_vp, _vp, _vp, _i64, _int, _vp, ctypes.c_char_p, _i64]),
@@ -289,6 +291,23 @@ class Assembler:
         return x, it.value, rr.value
 
     CONFIG = ("fused", "rebuild_qd", "rebuild_qo", "stream_qd", "stream_qo", "grid_cap", "rebuild_nt")
+
+    def lumped_mass(self, stream=None) -> torch.Tensor:
+        """M_t per dof (float64 CUDA tensor, n_rows), stream-ordered."""
+        m = torch.empty(self.n_rows, dtype=torch.float64, device="cuda")
+        _check(load().sta_lumped_mass(self._ctx, _dev_ptr(m), _stream_handle(stream)), self._ctx)
+        return m
+
+    def euler_step(self, u: torch.Tensor, v: torch.Tensor, f: torch.Tensor, rtol: float = 1e-10,
+                   max_iter: int = 20000, stream=None):
+        """One implicit-Euler step of eq. (9) with h = dt; u, v updated in place.
+        Returns (iterations, relative residual)."""
+        for t in (u, v, f):
+            _need_f64(t, self.n_rows)
+        it, rr = _int(0), _dbl(0.0)
+        _check(load().sta_euler_step(self._ctx, _dev_ptr(u), _dev_ptr(v), _dev_ptr(f), float(rtol), int(max_iter),
+                                     _stream_handle(stream), ctypes.byref(it), ctypes.byref(rr)), self._ctx)
+        return it.value, rr.value
 
     def set_config(self, fused=0, rebuild_qd=1, rebuild_qo=1, stream_qd=1, stream_qo=1, grid_cap=0, rebuild_nt=0):
         _check(load().sta_set_config(self._ctx, int(fused), int(rebuild_qd), int(rebuild_qo), int(stream_qd),
