@@ -605,6 +605,43 @@ def euler_section(torch, stafem, workloads, w, frames, cfg, args, rtol=1e-8):
     return out
 
 
+def connectivity_section(torch, stafem, w, frames, args):
+    """Connectivity rebuilt from the mask after every frame of the headline stream
+    (union-find over the active tets' vertices): time per rebuild and the component
+    count along the stream; each rebuild is repeated and must give identical labels."""
+    asm = stafem.Assembler.from_workload(w)
+    dfr = [stafem.upload_frame(ids, st) for ids, st in frames]
+    lab = torch.empty(w.n_tets, dtype=torch.int32, device="cuda")
+    import ctypes
+
+    lib = stafem.load()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    times, counts, stable = [], [], True
+    for ids, st in dfr:
+        asm.apply_edits(ids, st)
+        torch.cuda.synchronize()
+        torch.cuda._sleep(200000)
+        ev[0].record()
+        code = lib.sta_components(asm.handle, ctypes.c_void_p(lab.data_ptr()), None,
+                                  ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        ev[1].record()
+        ev[1].synchronize()
+        assert code == stafem.STA_OK
+        times.append(ev[0].elapsed_time(ev[1]) * 1e3)
+        again, k = asm.components()
+        stable = stable and bool(torch.equal(again, lab))
+        counts.append(k)
+    asm.close()
+    out = {"workload": "components of the active tets (shared-vertex adjacency) rebuilt after every frame of the "
+                       "headline stream",
+           "rebuild_us_median": round(float(np.median(times)), 3), "rebuild_us_max": round(float(np.max(times)), 3),
+           "components_initial": counts[0], "components_max": int(max(counts)), "components_final": counts[-1],
+           "repeat_labels_identical": stable}
+    log(f"[bench] connectivity: {out['rebuild_us_median']} us per rebuild, components {counts[0]} -> "
+        f"{max(counts)} -> {counts[-1]}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -694,6 +731,7 @@ def main():
         out["delta"] = delta_section(torch, stafem, w, frames, out["tuned_config"], step_s, args)
         out["proxy"] = proxy_section(torch, stafem, w, frames, args)
         out["euler"] = euler_section(torch, stafem, workloads, w, frames, out["tuned_config"], args)
+        out["connectivity"] = connectivity_section(torch, stafem, w, frames, args)
         r = workloads.make_refinement(args.seed)
         rf = r.frames[:24]
         rframes = rf + [(ids, (1 - st).astype(np.uint8)) for ids, st in reversed(rf)]

@@ -237,6 +237,15 @@ sta_status sta_lumped_mass(sta_ctx* ctx, double* m_dev, void* stream);
 sta_status sta_euler_step(sta_ctx* ctx, double* u_dev, double* v_dev, const double* f_dev, double rtol,
                           int max_iter, void* stream, int* iters_out, double* relres_out);
 
+/* Connectivity of the active tets (Sec. 3.6, Alg. 1: union-find rebuilt from
+ * the current mask).  Two active tets are connected when they share a vertex
+ * (the components of the assembled operator).  labels_dev (device, n_tets
+ * int32) receives, per tet, its component's smallest vertex id, or -1 for an
+ * inactive tet; labels do not depend on execution order.  *n_components
+ * (may be NULL) receives the number of components.  Synchronises `stream`
+ * (the host checks convergence after each pass). */
+sta_status sta_components(sta_ctx* ctx, int32_t* labels_dev, int64_t* n_components, void* stream);
+
 /* Execution configuration.
  *   fused       0: a frame is two launches (edit phase, touched phase);
  *               1: one persistent launch (both phases, grid barrier between).

@@ -23,7 +23,7 @@ LIB = os.path.join(HERE, "libstafem.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["pattern.cpp", "assembly.hip", "adjoint.hip", "cg.hip", "batch.hip", "probe.hip", "proxy.hip", "euler.hip", "api.hip"]
+SOURCES = ["pattern.cpp", "assembly.hip", "adjoint.hip", "cg.hip", "batch.hip", "probe.hip", "proxy.hip", "euler.hip", "connect.hip", "api.hip"]
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

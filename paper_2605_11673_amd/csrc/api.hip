@@ -791,6 +791,8 @@ void sta_destroy(sta_ctx* ctx)
         (void)hipEventDestroy(ev);
     if (ctx->cg_host)
         (void)hipHostFree(ctx->cg_host);
+    if (ctx->cc_host)
+        (void)hipHostFree(ctx->cc_host);
     free_all(ctx);
     delete ctx;
 }

@@ -137,6 +137,9 @@ struct sta_ctx {
     double* tet_ml = nullptr;       // per tet: lumped mass per vertex dof, (rho V) / 4
     bool tet_ml_stale = true;
     double* euler_ws = nullptr;     // implicit Euler: M_t, right-hand side, new u (3 x n_rows)
+    int32_t* cc_ws = nullptr;       // connectivity: parent and mark per node, 2 flags
+    uint32_t* cc_host = nullptr;    // pinned flag read back after each pass
+    int cc_passes = 0;              // passes of the last sta_components
     // batch layout: per mesh node / tet / value offsets (k+1 entries)
     std::vector<int64_t> node_off, tet_off, nnz_off;
     std::string errmsg;

@@ -60,6 +60,7 @@ SIGNATURES = {
     "sta_cg_solve": (_int, [_vp, _vp, _vp, _vp, _dbl, _int, _vp, ctypes.POINTER(_int), ctypes.POINTER(_dbl)]),
     "sta_lumped_mass": (_int, [_vp, _vp, _vp]),
     "sta_euler_step": (_int, [_vp, _vp, _vp, _vp, _dbl, _int, _vp, ctypes.POINTER(_int), ctypes.POINTER(_dbl)]),
+    "sta_components": (_int, [_vp, _vp, _i64p, _vp]),
     "sta_set_config": (_int, [_vp, _int, _int, _int, _int, _int, _int, _int]),
     "sta_get_config": (_int, [_vp, ctypes.POINTER(_int)]),
     "sta_autotune": (_int, [_vp, _vp, _vp, _i64, _int, _vp, ctypes.c_char_p, _i64]),
@@ -308,6 +309,13 @@ class Assembler:
         _check(load().sta_euler_step(self._ctx, _dev_ptr(u), _dev_ptr(v), _dev_ptr(f), float(rtol), int(max_iter),
                                      _stream_handle(stream), ctypes.byref(it), ctypes.byref(rr)), self._ctx)
         return it.value, rr.value
+
+    def components(self, stream=None):
+        """(labels int32 CUDA tensor (n_tets,), number of components); synchronises."""
+        lab = torch.empty(max(self.n_tets, 1), dtype=torch.int32, device="cuda")
+        k = _i64()
+        _check(load().sta_components(self._ctx, _dev_ptr(lab), ctypes.byref(k), _stream_handle(stream)), self._ctx)
+        return lab[: self.n_tets], k.value
 
     def set_config(self, fused=0, rebuild_qd=1, rebuild_qo=1, stream_qd=1, stream_qo=1, grid_cap=0, rebuild_nt=0):
         _check(load().sta_set_config(self._ctx, int(fused), int(rebuild_qd), int(rebuild_qo), int(stream_qd),
