@@ -716,7 +716,7 @@ sta_status sta_cg_solve(sta_ctx* ctx, const double* values_dev, const double* b_
     const int nparts = cg_partials(n);
     hipError_t e = hipSuccess;
     if (!ctx->cg_ws) {
-        e = dalloc(ctx, &ctx->cg_ws, (size_t)6 * n + nparts);
+        e = dalloc(ctx, &ctx->cg_ws, (size_t)7 * n + nparts);
         if (e == hipSuccess)
             e = dalloc(ctx, &ctx->cg_dpos, (size_t)n);
         if (e == hipSuccess)
@@ -741,7 +741,7 @@ sta_status sta_cg_solve(sta_ctx* ctx, const double* values_dev, const double* b_
     c.r = c.x + n;
     c.z = c.r + n;
     c.p = c.z + n;
-    c.q = c.p + n;
+    c.q = c.p + 2 * n;
     c.dinv = c.q + n;
     c.part = c.dinv + n;
     c.s = ctx->cg_s;
@@ -751,7 +751,8 @@ sta_status sta_cg_solve(sta_ctx* ctx, const double* values_dev, const double* b_
     while (e == hipSuccess) {
         const int count = max_iter - done_iters < chunk ? max_iter - done_iters : chunk;
         if (count > 0)
-            e = timed(ctx, STA_KERNEL_SOLVE, s, [&] { return launch_cg_iterations(c, count, max_iter, s); });
+            e = timed(ctx, STA_KERNEL_SOLVE, s,
+                      [&] { return launch_cg_iterations(c, done_iters, count, max_iter, s); });
         done_iters += count;
         if (e == hipSuccess)
             e = hipMemcpyAsync(ctx->cg_host, ctx->cg_s, sizeof(CgScalars), hipMemcpyDeviceToHost, s);

@@ -8,6 +8,14 @@
 // Dot products use a fixed reduction tree (per-workgroup tree, then one
 // workgroup over the partials in index order): results are reproducible
 // run to run.
+//
+// One iteration is four launches: the matrix-vector product (which also
+// forms the new search direction p = z + beta p on the fly, from a second
+// copy of p, so no separate direction pass is needed), alpha, the x / r / z
+// update, beta.  The product works per node: the three rows of a node share
+// one column list (3x3 blocks), so a group of lanes walks the node's
+// neighbours once, reading one column index and one 3-vector of p per
+// neighbour for all three rows.
 #include <hip/hip_runtime.h>
 
 #include "sta_internal.h"
@@ -17,7 +25,7 @@ namespace sta {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kRowLanes = 8;  // lanes per CSR row in the matrix-vector product
+constexpr int kNodeLanes = 16;  // lanes per node (three CSR rows) in the matrix-vector product
 
 // Workgroup sum of one value per thread, fixed tree; result valid in thread 0.
 __device__ __forceinline__ double block_sum(double x, double* sh)
@@ -34,10 +42,21 @@ __device__ __forceinline__ double block_sum(double x, double* sh)
 }
 
 // Sum of partials[0..n) by one workgroup: thread t adds t, t+256, ... in order, then a tree.
+// Eight loads are issued before their additions (same order of additions).
 __device__ __forceinline__ double reduce_partials(const double* __restrict__ p, int n, double* sh)
 {
     double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += kBlock)
+    int i = threadIdx.x;
+    for (; i + 7 * kBlock < n; i += 8 * kBlock) {
+        double t[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            t[k] = p[i + k * kBlock];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            acc = acc + t[k];
+    }
+    for (; i < n; i += kBlock)
         acc = acc + p[i];
     return block_sum(acc, sh);
 }
@@ -56,7 +75,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgView c, const double* __re
         c.x[r] = 0.0;
         c.r[r] = br;
         const double z = br * di;
-        c.p[r] = z;
+        c.z[r] = z;
+        c.p[r] = 0.0;  // p_0 = z_0 + 0 * 0, formed by the first product
+        c.p[c.n + r] = 0.0;
         rz = br * z;
         bb = br * br;
     }
@@ -79,34 +100,68 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_finish(CgView c, double rtol
         c.s->rz = rz;
         c.s->bnorm2 = bb;
         c.s->rr = bb;
+        c.s->beta = 0.0;
         c.s->tol2 = (rtol * rtol) * bb;
         c.s->iters = 0;
         c.s->done = bb == 0.0 ? 1 : 0;
     }
 }
 
-// q = A p, partial p.q.  kRowLanes lanes per row, fixed shuffle tree.
-__global__ __launch_bounds__(kBlock) void k_cg_spmv(CgView c)
+// p_new = z + beta p_old and q = A p_new, partial p_new . q.  kNodeLanes
+// lanes per node; lane l takes neighbours l, l + kNodeLanes, ...; the three
+// row sums are then combined by a fixed shuffle tree.  p_old is read, p_new
+// written only for the node's own rows, so the two never alias.
+__global__ __launch_bounds__(kBlock) void k_cg_spmv(CgView c, int cur)
 {
     __shared__ double sh[kBlock];
     if (c.s->done)
         return;
-    const int r = blockIdx.x * (kBlock / kRowLanes) + threadIdx.x / kRowLanes;
-    const int l = threadIdx.x & (kRowLanes - 1);
-    double acc = 0.0;
-    if (r < c.n) {
-        const int s0 = c.rowptr[r], s1 = c.rowptr[r + 1];
-        for (int s = s0 + l; s < s1; s += kRowLanes)
-            acc = acc + c.vals[s] * c.p[c.colidx[s]];
-    }
-#pragma unroll
-    for (int o = kRowLanes / 2; o > 0; o >>= 1)
-        acc = acc + __shfl_xor(acc, o, kRowLanes);
+    const double beta = c.s->beta;
+    const double* __restrict__ pold = c.p + (cur ? c.n : 0);
+    double* __restrict__ pnew = c.p + (cur ? 0 : c.n);
+    const int nn = c.n / 3;
+    const int group = threadIdx.x / kNodeLanes, l = threadIdx.x & (kNodeLanes - 1);
+    constexpr int kGroups = kBlock / kNodeLanes;
     double pq = 0.0;
-    if (r < c.n && l == 0) {
-        const double q = c.dinv[r] != 0.0 ? acc : 0.0;
-        c.q[r] = q;
-        pq = c.p[r] * q;
+    // grid-stride over nodes (the grid is capped, which bounds the partials
+    // alpha adds); every group of a workgroup runs the same number of rounds
+    for (int base_node = blockIdx.x * kGroups; base_node < nn; base_node += gridDim.x * kGroups) {
+        const int i = base_node + group;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        if (i < nn) {
+            const int base = c.rowptr[3 * i];
+            const int rl = c.rowptr[3 * i + 1] - base;
+            const int deg = rl / 3;
+            for (int k = l; k < deg; k += kNodeLanes) {
+                const int j = c.colidx[base + 3 * k] / 3;
+                const double* v = c.vals + base + 3 * k;
+                double pj[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    pj[q] = c.z[3 * j + q] + beta * pold[3 * j + q];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    a0 = a0 + v[q] * pj[q];
+                    a1 = a1 + v[rl + q] * pj[q];
+                    a2 = a2 + v[2 * rl + q] * pj[q];
+                }
+            }
+        }
+#pragma unroll
+        for (int o = kNodeLanes / 2; o > 0; o >>= 1) {
+            a0 = a0 + __shfl_xor(a0, o, kNodeLanes);
+            a1 = a1 + __shfl_xor(a1, o, kNodeLanes);
+            a2 = a2 + __shfl_xor(a2, o, kNodeLanes);
+        }
+        if (i < nn && l < 3) {
+            const int r = 3 * i + l;
+            const double acc = l == 0 ? a0 : (l == 1 ? a1 : a2);
+            const double q = c.dinv[r] != 0.0 ? acc : 0.0;
+            const double pr = c.z[r] + beta * pold[r];
+            pnew[r] = pr;
+            c.q[r] = q;
+            pq = pq + pr * q;
+        }
     }
     const double s = block_sum(pq, sh);
     if (threadIdx.x == 0)
@@ -123,17 +178,18 @@ __global__ __launch_bounds__(kBlock) void k_cg_alpha(CgView c, int nparts)
         c.s->alpha = c.s->rz / pq;
 }
 
-// x += alpha p, r -= alpha q, z = Dinv r; partial r.z and r.r
-__global__ __launch_bounds__(kBlock) void k_cg_update(CgView c)
+// x += alpha p_new, r -= alpha q, z = Dinv r; partial r.z and r.r
+__global__ __launch_bounds__(kBlock) void k_cg_update(CgView c, int cur)
 {
     __shared__ double sh[kBlock];
     if (c.s->done)
         return;
     const double alpha = c.s->alpha;
+    const double* __restrict__ pnew = c.p + (cur ? 0 : c.n);
     const int i = blockIdx.x * kBlock + threadIdx.x;
     double rz = 0.0, rr = 0.0;
     if (i < c.n) {
-        c.x[i] = c.x[i] + alpha * c.p[i];
+        c.x[i] = c.x[i] + alpha * pnew[i];
         const double r = c.r[i] - alpha * c.q[i];
         c.r[i] = r;
         const double z = r * c.dinv[i];
@@ -166,16 +222,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_beta(CgView c, int max_iter)
         if (rr <= c.s->tol2 || c.s->iters >= max_iter)
             c.s->done = 1;
     }
-}
-
-__global__ __launch_bounds__(kBlock) void k_cg_direction(CgView c)
-{
-    if (c.s->done)
-        return;
-    const double beta = c.s->beta;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < c.n)
-        c.p[i] = c.z[i] + beta * c.p[i];
 }
 
 __global__ __launch_bounds__(kBlock) void k_cg_output(CgView c, double* __restrict__ x)
@@ -211,11 +257,19 @@ hipError_t launch_diag_positions(const DevView& v, int32_t* dpos, hipStream_t s)
     return hipGetLastError();
 }
 
+// Matrix-vector product grid: one workgroup per 16 nodes, at most 8192 (a
+// wider grid keeps more gathers in flight than fewer, longer-running groups).
+int spmv_grid(int n)
+{
+    const int g = (int)blocks(n / 3, kBlock / kNodeLanes);
+    return g < 1 ? 1 : (g > 8192 ? 8192 : g);
+}
+
 // Size of the partial-sum buffer: two vector-kernel halves or one SpMV grid.
 int cg_partials(int n)
 {
     const int a = 2 * (int)blocks(n, kBlock);
-    const int b = (int)blocks(n, kBlock / kRowLanes);
+    const int b = spmv_grid(n);
     return a > b ? a : b;
 }
 
@@ -226,16 +280,16 @@ hipError_t launch_cg_init(const CgView& c, const double* b, double rtol, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_cg_iterations(const CgView& c, int count, int max_iter, hipStream_t s)
+hipError_t launch_cg_iterations(const CgView& c, int first, int count, int max_iter, hipStream_t s)
 {
-    const unsigned gs = blocks(c.n, kBlock / kRowLanes);
+    const unsigned gs = (unsigned)spmv_grid(c.n);
     const unsigned gv = blocks(c.n, kBlock);
-    for (int k = 0; k < count; ++k) {
-        hipLaunchKernelGGL(k_cg_spmv, dim3(gs), dim3(kBlock), 0, s, c);
+    for (int k = first; k < first + count; ++k) {
+        const int cur = k & 1;  // which copy of p holds the previous direction
+        hipLaunchKernelGGL(k_cg_spmv, dim3(gs), dim3(kBlock), 0, s, c, cur);
         hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(kBlock), 0, s, c, (int)gs);
-        hipLaunchKernelGGL(k_cg_update, dim3(gv), dim3(kBlock), 0, s, c);
+        hipLaunchKernelGGL(k_cg_update, dim3(gv), dim3(kBlock), 0, s, c, cur);
         hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(kBlock), 0, s, c, max_iter);
-        hipLaunchKernelGGL(k_cg_direction, dim3(gv), dim3(kBlock), 0, s, c);
     }
     return hipGetLastError();
 }

@@ -107,7 +107,7 @@ struct CgView {
     const int32_t* colidx;
     const double* vals;
     const int32_t* dpos;  // diagonal position per row, -1 if none
-    double *x, *r, *z, *p, *q, *dinv, *part;
+    double *x, *r, *z, *p, *q, *dinv, *part;  // p: two copies of n (previous / new direction)
     CgScalars* s;
 };
 
@@ -128,7 +128,7 @@ struct sta_ctx {
     int frame_grid_cap = 0; // 0: occupancy limit only
     int frame_max_grid = 0; // co-resident workgroups for the fused kernel (per stream_map)
     // lazily allocated workspaces
-    double* cg_ws = nullptr;        // 6 vectors of n_rows + partials
+    double* cg_ws = nullptr;        // 7 vectors of n_rows (two copies of p) + partials
     int32_t* cg_dpos = nullptr;
     sta::CgScalars* cg_s = nullptr;
     sta::CgScalars* cg_host = nullptr;  // pinned
@@ -205,7 +205,8 @@ hipError_t launch_slot_outer(int n_rows, const int32_t* rowptr, const int32_t* c
 hipError_t launch_diag_positions(const DevView& v, int32_t* dpos, hipStream_t s);
 int cg_partials(int n);
 hipError_t launch_cg_init(const CgView& c, const double* b, double rtol, hipStream_t s);
-hipError_t launch_cg_iterations(const CgView& c, int count, int max_iter, hipStream_t s);
+// Iterations first .. first+count-1 (the iteration index picks the copy of p).
+hipError_t launch_cg_iterations(const CgView& c, int first, int count, int max_iter, hipStream_t s);
 hipError_t launch_cg_output(const CgView& c, double* x, hipStream_t s);
 
 // Lumped mass and implicit Euler (euler.hip).
