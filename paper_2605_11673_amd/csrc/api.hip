@@ -236,6 +236,8 @@ sta_status build_context(const double* x, int64_t n_nodes, const int32_t* tets, 
     ALLOC(wg_err, 16 * n_tets / 256 + 4096);
     ALLOC(ctl, 1);
     ALLOC(c->dinc, 4 * n_tets);
+    TetRecord* trec = nullptr;
+    ALLOC(trec, n_tets);
 #undef ALLOC
     if (e != hipSuccess) {
         free_all(c);
@@ -275,6 +277,24 @@ sta_status build_context(const double* x, int64_t n_nodes, const int32_t* tets, 
     if (e == hipSuccess) e = upload(e2b, he2b.data(), he2b.size(), s);
     if (e == hipSuccess) e = upload(e2p, P.e2p.data(), P.e2p.size(), s);
     if (e == hipSuccess) e = upload(c->dinc, P.dinc.data(), P.dinc.size(), s);
+    {
+        std::vector<TetRecord> hr((size_t)n_tets);
+        for (int64_t t = 0; t < n_tets; ++t) {
+            TetRecord& r = hr[t];
+            std::memset(&r, 0, sizeof r);
+            for (int j = 0; j < 10; ++j) {
+                r.desc[j] = hd[he2b[10 * t + j]];
+                r.pos[j] = P.e2p[10 * t + j];
+            }
+            for (int a = 0; a < 4; ++a)
+                for (int k = 0; k < 3; ++k)
+                    r.X[3 * a + k] = x[3 * (int64_t)tets[4 * t + a] + k];
+            r.T = hT[t];
+            r.E = E[t];
+        }
+        if (e == hipSuccess) e = upload(trec, hr.data(), hr.size(), s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);  // hr is freed at the end of this block
+    }
     if (e == hipSuccess && n_tets > 0) e = hipMemsetAsync(estamp, 0, sizeof(uint32_t) * n_tets, s);
     if (e == hipSuccess && nb > 0) e = hipMemsetAsync(bstamp, 0, sizeof(uint32_t) * nb, s);
     if (e == hipSuccess && P.nnz > 0) e = hipMemsetAsync(values, 0, sizeof(double) * P.nnz, s);
@@ -290,6 +310,7 @@ sta_status build_context(const double* x, int64_t n_nodes, const int32_t* tets, 
     v.ndiag = ndiag;
     v.e2b = e2b;
     v.e2p = e2p;
+    v.trec = trec;
     v.cd = cd;
     v.co = co;
     v.values = values;
@@ -583,6 +604,8 @@ sta_status sta_set_params(sta_ctx* ctx, const double* x_dev, const double* E_dev
     double* xs = const_cast<double*>(ctx->v.xs);
     hipError_t e = launch_set_params(ctx->v, x_dev, E_dev, xs, xs + ctx->n_nodes, xs + 2 * ctx->n_nodes,
                                      const_cast<double*>(ctx->v.E), static_cast<hipStream_t>(stream));
+    if (e == hipSuccess)
+        e = launch_refresh_records(ctx->v, const_cast<TetRecord*>(ctx->v.trec), static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return hip_fail(ctx, e, "set_params launch");
     ctx->stale = true;

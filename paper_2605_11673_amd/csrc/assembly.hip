@@ -479,34 +479,40 @@ __device__ __forceinline__ int edit_lane(const DevView& v, int id, unsigned st, 
         return 0;
     }
     const bool slot = r < 10;
-    // round trip 1: everything indexed by the tet id, and the tet's stamp
-    uint32_t eb = 0;
+    const TetRecord* rc = v.trec + id;
+    // round trip 1: the tet's record (this lane's block descriptor and
+    // incidence position; vertex ids, coordinates and modulus for an
+    // activation), its mask bit and its stamp
+    BlockDesc bd = empty_desc();
     int ep = 0;
     if (slot) {
-        eb = (uint32_t)v.e2b[10 * (size_t)id + r];
-        ep = v.e2p[10 * (size_t)id + r];
+        bd = load_desc(rc->desc + r);
+        ep = rc->pos[r];
     }
     int4 t = make_int4(0, 0, 0, 0);
     double E = 0.0;
+    double X[4][3];
     if (slot && st) {
-        t = v.T[id];
-        E = v.E[id];
+        t = rc->T;
+        E = rc->E;
+        const dvec2* xp = reinterpret_cast<const dvec2*>(rc->X);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const dvec2 q = xp[k];
+            X[(2 * k) / 3][(2 * k) % 3] = q.x;
+            X[(2 * k + 1) / 3][(2 * k + 1) % 3] = q.y;
+        }
     }
     const uint8_t prev = v.mask[id];
     unsigned taken = 0u;
     if (r == 0)
         taken = atomicExch(&v.estamp[id], 1u);
-    // round trip 2: block claims, block descriptors, vertex coordinates
+    // round trip 2: the block claim (its result is needed only for the claim
+    // record, written last)
     const bool change = prev != st;
     unsigned claimed = 1u;
     if (slot && change)
-        claimed = atomicExch(&v.bstamp[eb], 1u);
-    BlockDesc bd = empty_desc();
-    if (slot)
-        bd = load_desc(v.desc + eb);
-    double X[4][3];
-    if (slot && st)
-        load_vertices(v, t, X);
+        claimed = atomicExch(&v.bstamp[bd.block], 1u);
     // the atomics' results pass through cross-lane moves, which the compiler
     // keeps in place, so their waits fall here and after the slot stores
     const int owner = __shfl(taken, (threadIdx.x & 63) & ~(kEditLanes - 1), 64) == 0u;
@@ -668,10 +674,15 @@ __global__ __launch_bounds__(kBlock) void k_touched(DevView v, const int32_t* __
     // need no branch (whose join would wait for them)
     const BlockDesc d = load_desc(lane ? v.rec + 10 * (size_t)i + j : &kNoClaim);
     const int id = *(lane && r == 0 ? ids + i : &kNoTet);
+    // the error bytes of every workgroup of the edit phase (its grid is sized
+    // by n_host), read before the device-side count so the loads overlap
+    const int g = n_host > 0 ? (n_host * kEditLanes + kBlock - 1) / kBlock : 1;
+    int bits = threadIdx.x < g ? v.wg_err[threadIdx.x] : 0;
+    for (int w = threadIdx.x + kBlock; w < g; w += kBlock)
+        bits |= v.wg_err[w];
     bool bad_n;
     const int n = frame_count(n_host, n_dev, bad_n);
-    // every workgroup of the edit phase's grid (sized by n_host) wrote its byte
-    const int fe = frame_error(v, n_host > 0 ? (n_host * kEditLanes + kBlock - 1) / kBlock : 1, &s_bits);
+    const int fe = block_or(bits, &s_bits);
     publish_frame(v, fe, n);
     if (lane && i < n)
         touched_lane<QD, QO>(v, d, id, fe, i, r, vi, q);
@@ -892,6 +903,22 @@ __global__ __launch_bounds__(kBlock) void k_set_params(int n_nodes, int n_tets, 
         Eout[i] = Ein[i];
 }
 
+__global__ __launch_bounds__(kBlock) void k_refresh_records(DevView v, TetRecord* __restrict__ trec)
+{
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= v.n_tets)
+        return;
+    const int4 t = v.T[e];
+    const int id[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        trec[e].X[3 * a + 0] = v.xs[id[a]];
+        trec[e].X[3 * a + 1] = v.ys[id[a]];
+        trec[e].X[3 * a + 2] = v.zs[id[a]];
+    }
+    trec[e].E = v.E[e];
+}
+
 inline unsigned blocks_for(int64_t threads)
 {
     return (unsigned)((threads + kBlock - 1) / kBlock);
@@ -1012,6 +1039,14 @@ hipError_t launch_frame(const DevView& v, const MapConfig& m, int grid, const in
     STA_MAPPINGS(LAUNCH)
 #undef LAUNCH
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_refresh_records(const DevView& v, TetRecord* trec, hipStream_t s)
+{
+    if (v.n_tets == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_refresh_records, dim3(blocks_for(v.n_tets)), dim3(kBlock), 0, s, v, trec);
+    return hipGetLastError();
 }
 
 hipError_t launch_set_params(const DevView& v, const double* x_aos, const double* E, double* xs, double* ys,

@@ -58,6 +58,21 @@ struct BlockDesc {
     int32_t block;   // block id
 };
 
+// Everything the edit phase reads about one candidate tet, packed in one
+// 512-byte record so that an edit needs a single memory round trip before
+// its atomics: the tet's 10 block descriptors (local pairs 00 11 22 33 | 01
+// 02 03 12 13 23), its vertex coordinates and modulus (copies, refreshed by
+// sta_set_params), its vertex ids and its 10 incidence positions.
+struct TetRecord {
+    BlockDesc desc[10];
+    double X[12];
+    int4 T;
+    double E;
+    int32_t pos[10];
+    int32_t pad[8];
+};
+static_assert(sizeof(TetRecord) == 512, "tet record is 512 bytes");
+
 // Everything the kernels need, passed by value.
 //
 // Invariant kept by every kernel: the contributions of an inactive tet are
@@ -79,6 +94,7 @@ struct DevView {
     // incidence positions (into cd for the first 4, into co for the other 6)
     const int32_t* e2b;
     const int32_t* e2p;
+    const TetRecord* trec;        // per tet: what the edit phase reads
     double* cd;                   // 6 unique values per diagonal incidence
     double* co;                   // 9 values per off-diagonal incidence (block orientation)
     double* values;               // CSR values
@@ -196,6 +212,8 @@ hipError_t launch_frame(const DevView& v, const MapConfig& m, int grid, const in
                         int32_t n_host, const int32_t* n_dev, hipStream_t s);
 hipError_t launch_set_params(const DevView& v, const double* x_aos, const double* E, double* xs, double* ys,
                              double* zs, double* Eout, hipStream_t s);
+// Copy the current coordinates and moduli into the tet records.
+hipError_t launch_refresh_records(const DevView& v, TetRecord* trec, hipStream_t s);
 
 // Adjoint and CG launchers (adjoint.hip, cg.hip).
 hipError_t launch_adjoint(const DevView& v, const double* gA, double* g_logE, double* g_x, double* xbar,
