@@ -231,7 +231,9 @@ sta_status build_context(const double* x, int64_t n_nodes, const int32_t* tets, 
     ALLOC(co, 54 * n_tets);
     ALLOC(estamp, n_tets);
     ALLOC(bstamp, nb);
-    ALLOC(rec, 10 * n_tets);
+    ALLOC(rec, 10 * n_tets + 160);
+    int32_t* rcount = nullptr;
+    ALLOC(rcount, 8 * ((16 * n_tets + 255) / 256 + 1));
     ALLOC(undo, n_tets);
     ALLOC(wg_err, 16 * n_tets / 256 + 4096);
     ALLOC(ctl, 1);
@@ -317,6 +319,7 @@ sta_status build_context(const double* x, int64_t n_nodes, const int32_t* tets, 
     v.estamp = estamp;
     v.bstamp = bstamp;
     v.rec = rec;
+    v.rcount = rcount;
     v.undo = undo;
     v.wg_err = wg_err;
     v.ctl = ctl;
@@ -517,44 +520,47 @@ sta_status sta_last_frame_stats(sta_ctx* ctx, void* stream, int64_t* out, int n_
         return STA_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipStreamSynchronize(s);
-    int32_t n_last = 0;
+    Ctl h{};
     if (e == hipSuccess)
-        e = hipMemcpy(&n_last, &ctx->v.ctl->last_n, sizeof(int32_t), hipMemcpyDeviceToHost);
-    const int64_t n = (n_last >= 0 && n_last <= ctx->n_tets) ? n_last : 0;
-    std::vector<BlockDesc> rc((size_t)n * 10);
+        e = hipMemcpy(&h, ctx->v.ctl, sizeof(Ctl), hipMemcpyDeviceToHost);
+    const int64_t n = (h.last_n >= 0 && h.last_n <= ctx->n_tets) ? h.last_n : 0;
+    const int64_t max_regions = 4 * ((16 * ctx->n_tets + 255) / 256 + 1);
+    const int64_t g = (h.last_regions >= 0 && h.last_regions <= max_regions) ? h.last_regions : 0;
+    std::vector<BlockDesc> rc((size_t)g * 40);
+    std::vector<int32_t> cnt((size_t)g * 2);
     std::vector<uint8_t> un((size_t)n);
-    int32_t ferr = 0;
-    if (e == hipSuccess && n > 0)
+    if (e == hipSuccess && g > 0)
         e = hipMemcpy(rc.data(), ctx->v.rec, sizeof(BlockDesc) * rc.size(), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && g > 0)
+        e = hipMemcpy(cnt.data(), ctx->v.rcount, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost);
     if (e == hipSuccess && n > 0)
         e = hipMemcpy(un.data(), ctx->v.undo, un.size(), hipMemcpyDeviceToHost);
-    if (e == hipSuccess)
-        e = hipMemcpy(&ferr, &ctx->v.ctl->frame_err, sizeof(int32_t), hipMemcpyDeviceToHost);
     if (e != hipSuccess)
         return hip_fail(ctx, e, "stats copy");
     int64_t st[STA_NUM_FRAME_STATS] = {0};
     st[7] = n;
-    st[8] = (n > 0 && ferr != 0) ? 1 : 0;
-    if (n > 0 && ferr == 0) {
-        for (int64_t i = 0; i < n; ++i) {
-            for (int j = 0; j < 10; ++j) {
-                const BlockDesc& d = rc[10 * i + j];
-                if (d.kind == 0) {
-                    st[0] += 1;
-                    st[2] += d.k1 - d.k0;
-                    st[4] += 9;
-                } else if (d.kind == 1) {
-                    st[1] += 1;
-                    st[3] += d.k1 - d.k0;
-                    st[4] += 18;
-                }
+    st[8] = (n > 0 && h.frame_err != 0) ? 1 : 0;
+    if (n > 0 && h.frame_err == 0) {
+        for (int64_t w = 0; w < g; ++w) {
+            for (int k = 0; k < cnt[2 * w] && k < 16; ++k) {
+                const BlockDesc& d = rc[40 * w + k];
+                st[0] += 1;
+                st[2] += d.k1 - d.k0;
+                st[4] += 9;
             }
+            for (int k = 0; k < cnt[2 * w + 1] && k < 24; ++k) {
+                const BlockDesc& d = rc[40 * w + 16 + k];
+                st[1] += 1;
+                st[3] += d.k1 - d.k0;
+                st[4] += 18;
+            }
+        }
+        for (int64_t i = 0; i < n; ++i)
             if (un[i] != 0xFF) {
                 st[5] += 1;
                 if (un[i] == 0)
                     st[6] += 1;
             }
-        }
     }
     for (int k = 0; k < n_out && k < STA_NUM_FRAME_STATS; ++k)
         out[k] = st[k];

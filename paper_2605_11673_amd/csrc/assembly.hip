@@ -30,6 +30,10 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kXcds = 8;
 constexpr int kEditLanes = 16;     // phase 1: one lane per block slot (10 used), power of two
+// Claimed blocks are compacted per edit-phase wave (64 / kEditLanes = 4
+// edits): at most 16 diagonal and 24 off-diagonal claims.
+constexpr int kRegionDiag = 16, kRegionOff = 24, kRegion = kRegionDiag + kRegionOff;
+constexpr int kRegionsPerBlock = kBlock / 64;
 
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
@@ -456,7 +460,8 @@ __device__ __forceinline__ int frame_count(int32_t n_host, const int32_t* n_dev,
 // edit, lane r < 10 owns block slot r.  Validate the edit; lane 0 takes the
 // tet's stamp (a second edit of the same tet in this frame finds it taken:
 // duplicate).  If the state changes, each slot lane claims its block (first
-// claimant wins; the claim record carries the block descriptor), the owner
+// claimant wins; the claim's kind and block descriptor are returned in ckind
+// (-1: no claim) and cbd for the wave's compaction), the owner
 // flips the mask bit and the slot lanes rewrite the tet's 78 contribution
 // slots (element matrix on activation, zeros on deactivation).  Returns the
 // lane's error bits.  All 16 lanes of the edit must call it together.
@@ -466,12 +471,10 @@ __device__ __forceinline__ int frame_count(int32_t n_host, const int32_t* n_dev,
 // mask bit, vertex ids, modulus) and then the block descriptors and vertex
 // coordinates are issued before the first atomic or store, which the compiler
 // could not move them across.
-__device__ __forceinline__ int edit_lane(const DevView& v, int id, unsigned st, int i, int r)
+__device__ __forceinline__ int edit_lane(const DevView& v, int id, unsigned st, int i, int r, int& ckind,
+                                         BlockDesc& cbd)
 {
-    BlockDesc* rec = v.rec + 10 * (size_t)i;
     if (id < 0 || id >= v.n_tets || st > 1u) {
-        if (r < 10)
-            store_desc(rec + r, empty_desc());
         if (r == 0) {
             v.undo[i] = 0xFF;
             return ERR_RANGE;
@@ -530,73 +533,98 @@ __device__ __forceinline__ int edit_lane(const DevView& v, int id, unsigned st, 
             store_slot(v, t, G, r, ep, st != 0u);
         }
     }
-    // the claim record is written last, so the claim's round trip overlaps the slot arithmetic
+    // the claim is consumed last, so the claim's round trip overlaps the slot
+    // arithmetic; the caller compacts the wave's claims into its region
     claimed = __shfl(claimed, threadIdx.x & 63, 64);
-    if (slot)
-        store_desc(rec + r, claimed == 0u ? bd : empty_desc());
+    if (slot && claimed == 0u) {
+        ckind = r < 4 ? 0 : 1;
+        cbd = bd;
+    }
     if (r == 0)
         v.undo[i] = (owner && change) ? prev : (uint8_t)0xFF;
     return bits;
 }
 
-// Lanes per edit in phase 2: 4 diagonal blocks x 6 values x QD lanes, then
-// 6 off-diagonal blocks x 9 values x QO lanes, rounded up to 16 so that the
-// lane groups of every edit stay aligned inside a wave.
+// Phase 2 lanes: per claim region, 6 QD lanes for each of its 16 diagonal
+// records then 9 QO lanes for each of its 24 off-diagonal records, padded to
+// whole waves; after all regions, one lane per edit (stamp release,
+// rollback).  Every lane group of Q starts at a multiple of Q, so it never
+// crosses a wave boundary.  Lanes of records past a region's count have
+// nothing to do, and since each region fills from its start, whole waves of
+// them exit at once.
 template <int QD, int QO>
 struct Phase2 {
-    static constexpr int kDiag = 24 * QD;
-    static constexpr int kLanes = (24 * QD + 54 * QO + 15) / 16 * 16;
+    static constexpr int LD = 6 * QD, LO = 9 * QO;
+    static constexpr int kDiagLanes = kRegionDiag * LD;
+    // padded to whole waves, so that every region starts at a wave boundary
+    static constexpr int kRegionLanes = (kDiagLanes + kRegionOff * LO + 63) / 64 * 64;
 };
 
-// Phase 2 lane r of an edit: which claim record (j) and which of its values
-// (vi), and the lane's place q in the value's lane group.  Returns false for
-// the padding lanes past the last off-diagonal value.
+// Decode phase-2 lane t: a record lane (region w, slot in the region, value
+// vi, place q in the value's lane group), an edit lane (edit = index into
+// the edit list, returned in w with slot = -1) or a padding lane (slot = -2).
 template <int QD, int QO>
-__device__ __forceinline__ bool touched_slot(int r, int& j, int& vi, int& q)
+__device__ __forceinline__ void touched_role(int64_t t, int regions, int& w, int& slot, int& vi, int& q)
 {
-    if (r < Phase2<QD, QO>::kDiag) {
-        j = r / (6 * QD);
-        const int rem = r - j * (6 * QD);
+    using P = Phase2<QD, QO>;
+    const int64_t rl = (int64_t)regions * P::kRegionLanes;
+    if (t >= rl) {
+        w = (int)(t - rl);
+        slot = -1;
+        vi = q = 0;
+        return;
+    }
+    w = (int)(t / P::kRegionLanes);
+    const int u = (int)(t - (int64_t)w * P::kRegionLanes);
+    if (u < P::kDiagLanes) {
+        slot = u / P::LD;
+        const int rem = u - slot * P::LD;
         vi = rem / QD;
         q = rem - vi * QD;
-        return true;
+    } else {
+        const int u2 = u - P::kDiagLanes;
+        const int k = u2 / P::LO;
+        if (k >= kRegionOff) {
+            slot = -2;
+            vi = q = 0;
+            return;
+        }
+        slot = kRegionDiag + k;
+        const int rem = u2 - k * P::LO;
+        vi = rem / QO;
+        q = rem - vi * QO;
     }
-    const int rr = r - Phase2<QD, QO>::kDiag;
-    j = 4 + rr / (9 * QO);
-    const int rem = rr - (j - 4) * (9 * QO);
-    vi = rem / QO;
-    q = rem - vi * QO;
-    return rr < 54 * QO;
 }
 
-// Phase 2 for lane r of edit i (tet id), given its claim record d (loaded
-// by the caller before the frame's error bits are known, so that the two
-// round trips overlap).  fe: the frame's error bits.  Without an error the
-// lane group re-sums its value if the edit claimed the block; with one, lane
-// 0 undoes the edit's mask flip and slot rewrite.  Either way the frame's
-// stamps are cleared for the next frame.
+// Phase 2, record lane: re-sum value vi of a claimed block (lane group of Q,
+// place q) unless the frame has an error; the first lane of the record
+// releases the block's claim stamp either way.
 template <int QD, int QO>
-__device__ __forceinline__ void touched_lane(const DevView& v, const BlockDesc& d, int id, int fe, int i, int r,
-                                             int vi, int q)
+__device__ __forceinline__ void touched_record(const DevView& v, const BlockDesc& d, int fe, int vi, int q)
 {
-    if (!fe && d.kind >= 0)
+    if (!fe)
         block_value<QD, QO>(v, d, vi, q, (threadIdx.x & 63) - q);
-    if (vi == 0 && q == 0 && d.kind >= 0)
+    if (vi == 0 && q == 0)
         v.bstamp[d.block] = 0u;
-    if (r == 0 && id >= 0 && id < v.n_tets) {
-        v.estamp[id] = 0u;
-        const uint8_t u = v.undo[i];
-        if (fe && u != 0xFF) {
-            int ep[10];
+}
+
+// Phase 2, edit lane for edit i (tet id, undo byte u): release the tet stamp
+// and, if the frame has an error, undo the edit's mask flip and slot rewrite.
+__device__ __forceinline__ void touched_edit(const DevView& v, int id, uint8_t u, int fe)
+{
+    if (id < 0 || id >= v.n_tets)
+        return;
+    v.estamp[id] = 0u;
+    if (fe && u != 0xFF) {
+        int ep[10];
 #pragma unroll
-            for (int k = 0; k < 10; ++k)
-                ep[k] = v.e2p[10 * (size_t)id + k];
-            v.mask[id] = u;
-            if (u)
-                store_element(v, id, v.T[id], ep);
-            else
-                zero_element(v, ep);
-        }
+        for (int k = 0; k < 10; ++k)
+            ep[k] = v.e2p[10 * (size_t)id + k];
+        v.mask[id] = u;
+        if (u)
+            store_element(v, id, v.T[id], ep);
+        else
+            zero_element(v, ep);
     }
 }
 
@@ -621,13 +649,33 @@ __device__ __forceinline__ int frame_error(const DevView& v, int g, int* s_bits)
     return block_or(bits, s_bits);
 }
 
-__device__ __forceinline__ void publish_frame(const DevView& v, int fe, int n)
+__device__ __forceinline__ void publish_frame(const DevView& v, int fe, int n, int regions)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         v.ctl->frame_err = fe;
         v.ctl->last_n = n;
+        v.ctl->last_regions = regions;
         if (fe)
             atomicOr(&v.ctl->err, fe);
+    }
+}
+
+// Compact the wave's claims into claim region `region`: diagonal claims
+// first, then off-diagonal ones, each in lane order; lane 0 records the two
+// counts.  Called by every lane of the wave (ckind = -1: no claim).
+__device__ __forceinline__ void compact_claims(const DevView& v, int64_t region, int ckind, const BlockDesc& cbd)
+{
+    const uint64_t dm = __ballot(ckind == 0);
+    const uint64_t om = __ballot(ckind == 1);
+    const uint64_t below = __lanemask_lt();
+    BlockDesc* base = v.rec + region * kRegion;
+    if (ckind == 0)
+        store_desc(base + __popcll(dm & below), cbd);
+    else if (ckind == 1)
+        store_desc(base + kRegionDiag + __popcll(om & below), cbd);
+    if ((threadIdx.x & 63) == 0) {
+        v.rcount[2 * region] = __popcll(dm);
+        v.rcount[2 * region + 1] = __popcll(om);
     }
 }
 
@@ -650,8 +698,11 @@ __global__ __launch_bounds__(kBlock) void k_edits(DevView v, const int32_t* __re
     bool bad_n;
     const int n = frame_count(n_host, n_dev, bad_n);
     int bits = (bad_n && gt == 0) ? ERR_RANGE : 0;
+    int ckind = -1;
+    BlockDesc cbd;
     if (i < n)
-        bits |= edit_lane(v, id, st, i, gt - i * kEditLanes);
+        bits |= edit_lane(v, id, st, i, gt - i * kEditLanes, ckind, cbd);
+    compact_claims(v, gt / 64, ckind, cbd);
     bits = block_or(bits, &s_bits);
     if (threadIdx.x == 0)
         v.wg_err[blockIdx.x] = (uint8_t)bits;
@@ -663,29 +714,34 @@ __global__ __launch_bounds__(kBlock) void k_touched(DevView v, const int32_t* __
                                                     const int32_t* __restrict__ n_dev)
 {
     __shared__ int s_bits;
-    constexpr int L = Phase2<QD, QO>::kLanes;
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int i = (int)(t / L);
-    const int r = (int)(t - (int64_t)i * L);
-    int j, vi, q;
-    const bool lane = touched_slot<QD, QO>(r, j, vi, q) && i < n_host;
-    // claim record and tet id load together with the count and the error
-    // bytes; lanes without them read fixed empty values instead, so the loads
-    // need no branch (whose join would wait for them)
-    const BlockDesc d = load_desc(lane ? v.rec + 10 * (size_t)i + j : &kNoClaim);
-    const int id = *(lane && r == 0 ? ids + i : &kNoTet);
-    // the error bytes of every workgroup of the edit phase (its grid is sized
-    // by n_host), read before the device-side count so the loads overlap
-    const int g = n_host > 0 ? (n_host * kEditLanes + kBlock - 1) / kBlock : 1;
-    int bits = threadIdx.x < g ? v.wg_err[threadIdx.x] : 0;
-    for (int w = threadIdx.x + kBlock; w < g; w += kBlock)
-        bits |= v.wg_err[w];
+    // the edit phase ran `edit_wgs` workgroups of kRegionsPerBlock waves, each wave one claim region
+    const int edit_wgs = n_host > 0 ? (n_host * kEditLanes + kBlock - 1) / kBlock : 1;
+    const int regions = edit_wgs * kRegionsPerBlock;
+    int w, slot, vi, q;
+    touched_role<QD, QO>((int64_t)blockIdx.x * kBlock + threadIdx.x, regions, w, slot, vi, q);
+    // claim record and count, or the edit's id and undo byte, load together
+    // with the error bytes and the device-side count; lanes without them read
+    // fixed empty values instead, so the loads need no branch
+    const bool rec_lane = slot >= 0;
+    const bool edit_lane_ = slot == -1 && w < n_host;
+    const BlockDesc d = load_desc(rec_lane ? v.rec + (size_t)w * kRegion + slot : &kNoClaim);
+    const int cnt = rec_lane ? v.rcount[2 * w + (slot >= kRegionDiag ? 1 : 0)] : 0;
+    const int id = *(edit_lane_ ? ids + w : &kNoTet);
+    const uint8_t u = edit_lane_ ? v.undo[w] : (uint8_t)0xFF;
+    // the error bytes of every workgroup of the edit phase
+    int bits = threadIdx.x < edit_wgs ? v.wg_err[threadIdx.x] : 0;
+    for (int k = threadIdx.x + kBlock; k < edit_wgs; k += kBlock)
+        bits |= v.wg_err[k];
     bool bad_n;
     const int n = frame_count(n_host, n_dev, bad_n);
     const int fe = block_or(bits, &s_bits);
-    publish_frame(v, fe, n);
-    if (lane && i < n)
-        touched_lane<QD, QO>(v, d, id, fe, i, r, vi, q);
+    publish_frame(v, fe, n, regions);
+    if (rec_lane) {
+        if (slot - (slot >= kRegionDiag ? kRegionDiag : 0) < cnt)
+            touched_record<QD, QO>(v, d, fe, vi, q);
+    } else if (edit_lane_ && w < n) {
+        touched_edit(v, id, u, fe);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -865,12 +921,18 @@ __global__ __launch_bounds__(kBlock) void k_frame(DevView v, const int32_t* __re
     __shared__ int s_ok;
     bool bad_n;
     const int n = frame_count(n_host, n_dev, bad_n);
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    const int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    int bits = (bad_n && t0 == 0) ? ERR_RANGE : 0;
-    for (int64_t t = t0; t < (int64_t)n * kEditLanes; t += stride) {
+    const int regions = (n_host > 0 ? (n_host * kEditLanes + kBlock - 1) / kBlock : 1) * kRegionsPerBlock;
+    int bits = (bad_n && blockIdx.x == 0 && threadIdx.x == 0) ? ERR_RANGE : 0;
+    // phase 1 over whole waves (one claim region each), so that every lane of
+    // a wave runs the compaction together
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < (int64_t)regions * 64;
+         t += (int64_t)gridDim.x * kBlock) {
         const int i = (int)(t / kEditLanes);
-        bits |= edit_lane(v, ids[i], states[i], i, (int)(t - (int64_t)i * kEditLanes));
+        int ckind = -1;
+        BlockDesc cbd;
+        if (i < n)
+            bits |= edit_lane(v, ids[i], states[i], i, (int)(t - (int64_t)i * kEditLanes), ckind, cbd);
+        compact_claims(v, t / 64, ckind, cbd);
     }
     bits = block_or(bits, &s_bits);
     if (threadIdx.x == 0)
@@ -878,14 +940,18 @@ __global__ __launch_bounds__(kBlock) void k_frame(DevView v, const int32_t* __re
     if (!grid_barrier(v.ctl, gridDim.x, &s_ok))
         return;
     const int fe = frame_error(v, gridDim.x, &s_bits);
-    publish_frame(v, fe, n);
-    constexpr int L = Phase2<QD, QO>::kLanes;
-    for (int64_t t = t0; t < (int64_t)n * L; t += stride) {
-        const int i = (int)(t / L);
-        const int r = (int)(t - (int64_t)i * L);
-        int j, vi, q;
-        if (touched_slot<QD, QO>(r, j, vi, q))
-            touched_lane<QD, QO>(v, load_desc(v.rec + 10 * (size_t)i + j), r == 0 ? ids[i] : -1, fe, i, r, vi, q);
+    publish_frame(v, fe, n, regions);
+    const int64_t total = (int64_t)regions * Phase2<QD, QO>::kRegionLanes + n_host;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total; t += (int64_t)gridDim.x * kBlock) {
+        int w, slot, vi, q;
+        touched_role<QD, QO>(t, regions, w, slot, vi, q);
+        if (slot >= 0) {
+            const int c = v.rcount[2 * w + (slot >= kRegionDiag ? 1 : 0)];
+            if (slot - (slot >= kRegionDiag ? kRegionDiag : 0) < c)
+                touched_record<QD, QO>(v, load_desc(v.rec + (size_t)w * kRegion + slot), fe, vi, q);
+        } else if (slot == -1 && w < n) {
+            touched_edit(v, ids[w], v.undo[w], fe);
+        }
     }
 }
 
@@ -986,8 +1052,9 @@ hipError_t launch_touched_phase(const DevView& v, const MapConfig& m, const int3
 {
 #define LAUNCH(QD, QO)                                                                                      \
     if (m.qd == QD && m.qo == QO) {                                                                         \
-        const int64_t lanes = (int64_t)n_host * Phase2<QD, QO>::kLanes;                                     \
-        launch_kernel(&k_touched<QD, QO>, dim3(n_host > 0 ? blocks_for(lanes) : 1u), dim3(kBlock), 0, s, v, \
+        const int64_t regions = (n_host > 0 ? ((int64_t)n_host * kEditLanes + kBlock - 1) / kBlock : 1) * kRegionsPerBlock; \
+        const int64_t lanes = regions * Phase2<QD, QO>::kRegionLanes + n_host;                              \
+        launch_kernel(&k_touched<QD, QO>, dim3(blocks_for(lanes)), dim3(kBlock), 0, s, v,                 \
                            ids, n_host, n_dev);                                                             \
         return hipGetLastError();                                                                           \
     }
@@ -1018,10 +1085,11 @@ int frame_grid_for(const MapConfig& m, int32_t n_host, int max_grid, int grid_ca
     int L = 16;
 #define LANES(QD, QO)                 \
     if (m.qd == QD && m.qo == QO)     \
-        L = Phase2<QD, QO>::kLanes;
+        L = Phase2<QD, QO>::kRegionLanes;
     STA_MAPPINGS(LANES)
 #undef LANES
-    const int64_t want = n_host > 0 ? ((int64_t)n_host * L + kBlock - 1) / kBlock : 1;
+    const int64_t regions = (n_host > 0 ? ((int64_t)n_host * kEditLanes + kBlock - 1) / kBlock : 1) * kRegionsPerBlock;
+    const int64_t want = (regions * L + n_host + kBlock - 1) / kBlock;
     int64_t g = want < max_grid ? want : max_grid;
     if (grid_cap > 0 && g > grid_cap)
         g = grid_cap;

@@ -29,7 +29,8 @@ struct Ctl {
     int32_t last_n;      // edit count of the last frame (statistics; also right under graph replay)
     uint32_t bar_count;  // grid barrier of the fused frame kernel: arrivals
     uint32_t bar_gen;    // and generation
-    int32_t pad[2];
+    int32_t last_regions;  // claim regions of the last frame (one per edit-phase wave of 4 edits)
+    int32_t pad;
 };
 
 // Slot mapping: lanes per block value for diagonal / off-diagonal blocks
@@ -103,7 +104,11 @@ struct DevView {
     // the reduce phase clears the ones it set.
     uint32_t* estamp;             // per tet: taken by an edit of this frame
     uint32_t* bstamp;             // per block: claimed in this frame
-    BlockDesc* rec;               // per edit: 10 claim records (kind -1 = not claimed)
+    // Claimed blocks of the frame, compacted per edit-phase wave (4 edits):
+    // region w holds up to 16 diagonal then 24 off-diagonal block
+    // descriptors; rcount[2w], rcount[2w+1] say how many of each are valid.
+    BlockDesc* rec;
+    int32_t* rcount;
     uint8_t* undo;                // per edit: previous mask value, 0xFF = nothing to undo
     uint8_t* wg_err;              // per edit-phase workgroup: its error bits (always written)
     Ctl* ctl;
