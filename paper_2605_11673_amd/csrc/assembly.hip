@@ -857,6 +857,7 @@ __global__ __launch_bounds__(kBlock) void k_delta_edits(DevView v, const int32_t
     if (gt == 0) {
         v.ctl->last_n = n;
         v.ctl->frame_err = 0;
+        v.ctl->last_regions = 0;  // the delta policy claims no blocks
     }
 }
 

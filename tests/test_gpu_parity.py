@@ -260,3 +260,37 @@ def test_device_count_and_graph_replay():
     assert asm.status_sync() == S.STA_ERANGE
     assert_bitwise(gpu_values(asm), v0, "out-of-range device count")
     asm.close()
+
+
+def test_maximum_size_frames():
+    """Frames as large as the candidate pool: every tet deleted in one frame (the matrix
+    becomes all +0.0, no -0.0), every tet re-added in one frame (the initial bits come
+    back), then a random half toggled with random states (no-ops included), each frame's
+    ids in random order; also through the device-count entry point at full capacity."""
+    S = stafem()
+    w = W.make_fracture(seed=11, n=12, counts=[10])
+    pat = oracle.pattern(w.n_nodes, w.tets)
+    asm = S.Assembler.from_workload(w)
+    v0 = gpu_values(asm)
+    g = np.random.default_rng(11)
+    every = g.permutation(w.n_tets).astype(np.int32)
+    asm.apply_edits(*S.upload_frame(every, np.zeros(w.n_tets, np.uint8)))
+    zero = gpu_values(asm)
+    assert_bitwise(zero, oracle.rebuild_workload(w, np.zeros(w.n_tets, np.uint8), pat), "all deleted")
+    assert not np.any(np.signbit(zero)) and not np.any(zero)
+    assert asm.last_frame_stats()["edits"] == w.n_tets
+    asm.apply_edits(*S.upload_frame(every, np.ones(w.n_tets, np.uint8)))
+    assert_bitwise(gpu_values(asm), v0, "all re-added")
+    half = g.choice(w.n_tets, size=w.n_tets // 2, replace=False).astype(np.int32)
+    st = g.integers(0, 2, size=len(half)).astype(np.uint8)
+    ids_d = torch.zeros(w.n_tets, dtype=torch.int32, device="cuda")
+    st_d = torch.zeros(w.n_tets, dtype=torch.uint8, device="cuda")
+    n_d = torch.tensor([len(half)], dtype=torch.int32, device="cuda")
+    ids_d[:len(half)].copy_(torch.from_numpy(half))
+    st_d[:len(half)].copy_(torch.from_numpy(st))
+    asm.apply_edits_dev(ids_d, st_d, n_d)
+    mask = np.ones(w.n_tets, np.uint8)
+    mask[half] = st
+    assert_bitwise(gpu_values(asm), oracle.rebuild_workload(w, mask, pat), "random half, device count")
+    assert asm.status_sync() == S.STA_OK
+    asm.close()

@@ -189,3 +189,23 @@ def test_graph_replay_device_count():
     assert px.status_sync() == Sm.STA_ERANGE
     check(px, w, mask, pat, "after bad count")
     px.close()
+
+
+def test_maximum_size_frames():
+    """Every tet deleted in one frame (all edges inactive: off-diagonal +0.0, diagonal
+    eps), then every tet re-added (the initial state back)."""
+    Sm = S()
+    w = W.make_fracture(seed=12, n=10, counts=[10])
+    pat = P.proxy_pattern(w.n_nodes, w.tets)
+    px = Sm.Proxy.from_workload(w, EPS)
+    s0 = state(px)
+    every = np.random.default_rng(12).permutation(w.n_tets).astype(np.int32)
+    px.apply_edits(*Sm.upload_frame(every, np.zeros(w.n_tets, np.uint8)))
+    check(px, w, np.zeros(w.n_tets, np.uint8), pat, "all deleted")
+    v, c, d = state(px)
+    assert not np.any(c) and not np.any(d) and set(np.unique(v)) <= {0.0, EPS}
+    px.apply_edits(*Sm.upload_frame(every, np.ones(w.n_tets, np.uint8)))
+    for a, b in zip(state(px), s0):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    assert px.status_sync() == Sm.STA_OK
+    px.close()
