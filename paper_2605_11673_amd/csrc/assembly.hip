@@ -317,25 +317,123 @@ __device__ __forceinline__ void store_desc(BlockDesc* p, const BlockDesc& d)
 // ---------------------------------------------------------------------------
 
 // Every candidate: active -> element matrix into its slots, inactive -> zeros.
+// One lane per tet.  A tet's ten slot chunks lie far apart (each in its
+// block's incidence segment), so lanes storing their own chunks would send
+// one partial-line request per lane and store.  Instead each wave stages one
+// slot of its 64 tets at a time in LDS and stores it cooperatively:
+// neighbouring lanes write neighbouring parts of the same chunk, and the
+// memory pipeline merges them into a few line requests.
 template <bool NT>
 __global__ __launch_bounds__(kBlock) void k_element(DevView v)
 {
+    __shared__ double s_stage[kBlock / 64][64 * 9];
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
-    const int e = wg * kBlock + threadIdx.x;
-    if (e >= v.n_tets)
+    const int base = wg * kBlock + (threadIdx.x & ~63);  // the wave's first tet
+    if (base >= v.n_tets)
         return;
+    const int lane = threadIdx.x & 63;
+    const int e = base + lane;
+    const int nw = v.n_tets - base < 64 ? v.n_tets - base : 64;  // tets of this wave
+    const bool valid = lane < nw;
     int pos[10];
 #pragma unroll
     for (int j = 0; j < 10; ++j)
-        pos[j] = v.e2p[10 * (size_t)e + j];
-    if (v.mask[e])
-        store_element<NT>(v, e, v.T[e], pos);
-    else
-        zero_element<NT>(v, pos);
+        pos[j] = valid ? v.e2p[10 * (size_t)e + j] : 0;
+    const bool active = valid && v.mask[e];
+    Geo G;
+    int4 t = make_int4(0, 1, 2, 3);
+    if (active) {
+        t = v.T[e];
+        element_geometry(v, e, t, G);
+        if (G.det == 0.0)
+            atomicOr(&v.ctl->err, ERR_DEGENERATE);
+    }
+    double* buf = s_stage[threadIdx.x >> 6];
+    // LDS accesses of one wave complete in issue order; the wavefront-scope
+    // fences only keep the compiler from moving them across the exchange
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        if (active) {
+            const double s = dot3(G.g[a], G.g[a]);
+            buf[6 * lane + 0] = entry(G.g[a], G.g[a], s, G, 0, 0, true);
+            buf[6 * lane + 1] = entry(G.g[a], G.g[a], s, G, 0, 1, true);
+            buf[6 * lane + 2] = entry(G.g[a], G.g[a], s, G, 0, 2, true);
+            buf[6 * lane + 3] = entry(G.g[a], G.g[a], s, G, 1, 1, true);
+            buf[6 * lane + 4] = entry(G.g[a], G.g[a], s, G, 1, 2, true);
+            buf[6 * lane + 5] = entry(G.g[a], G.g[a], s, G, 2, 2, true);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                buf[6 * lane + k] = 0.0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // 64 chunks of 48 B = 192 pieces of 16 B, three per lane
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int p = lane + 64 * j, m = p / 3, k = p - 3 * m;
+            const int pm = __shfl(pos[a], m, 64);
+            if (m < nw)
+                st2<NT>(v.cd + 6 * (size_t)pm + 2 * k, buf[6 * m + 2 * k], buf[6 * m + 2 * k + 1]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    const int id[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        if (active) {
+            const bool sw = id[PA[q]] > id[PB[q]];
+            double ga[3], gb[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                ga[i] = sw ? G.g[PB[q]][i] : G.g[PA[q]][i];
+                gb[i] = sw ? G.g[PA[q]][i] : G.g[PB[q]][i];
+            }
+            const double s = dot3(ga, gb);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    buf[9 * lane + 3 * i + j] = entry(ga, gb, s, G, i, j, false);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                buf[9 * lane + k] = 0.0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // 64 chunks of 72 B (8-byte aligned) = 576 doubles, nine per lane
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            const int p = lane + 64 * j, m = p / 9, k = p - 9 * m;
+            const int pm = __shfl(pos[4 + q], m, 64);
+            if (m < nw)
+                st<NT>(v.co + 9 * (size_t)pm + k, buf[9 * m + k]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
 }
 
-// Lanes: 6*QD per diagonal block (section padded to whole waves), then 9*QO
-// per off-diagonal block.
+// Off-diagonal value vi of block d with one lane per value (QO = 1), the
+// block's 9 lanes in one wave from wave lane b0.  The mirror is written
+// transposed through a shuffle (lane (p, r) writes mirror entry (p, r), the
+// value of lane (r, p)), so that lanes 3p..3p+2 write one 24-byte row piece
+// of the block and one of its mirror.
+template <bool NT>
+__device__ __forceinline__ void off_value_rows(const DevView& v, const BlockDesc& d, int vi, int b0)
+{
+    const double acc = seg_sum<1, OffChunk<1>::CH, NT>(v.co, 9, vi, d.k0, d.k1, 0, b0 + vi);
+    const int p = vi / 3, r = vi - 3 * (vi / 3);
+    const double tr = __shfl(acc, b0 + 3 * r + p, 64);
+    st<NT>(v.values + d.up + p * d.rl + r, acc);
+    st<NT>(v.values + d.lo + p * d.rlj + r, tr);
+}
+
+// Lanes: 6*QD per diagonal block (section padded to whole waves), then the
+// off-diagonal blocks: for QO = 1, 7 blocks of 9 lanes per wave (lane 63
+// idle, so that a block never straddles two waves), else 9*QO per block.
 template <int QD, int QO, bool NT>
 __global__ __launch_bounds__(kBlock) void k_reduce_all(DevView v, int64_t diag_lanes)
 {
@@ -351,6 +449,14 @@ __global__ __launch_bounds__(kBlock) void k_reduce_all(DevView v, int64_t diag_l
         block_value<QD, QO, NT>(v, load_desc(v.desc + b), rem / QD, q, lane - q);
     } else {
         const int64_t u = t - diag_lanes;
+        if (QO == 1) {
+            const int l = (int)(u & 63);  // = lane: diag_lanes is a multiple of 64
+            const int o1 = (int)(u >> 6) * 7 + l / 9;
+            if (l == 63 || o1 >= v.no)
+                return;
+            off_value_rows<NT>(v, load_desc(v.desc + v.nd + o1), l % 9, lane - l % 9);
+            return;
+        }
         const int o = (int)(u / (9 * QO));
         if (o >= v.no)
             return;
@@ -1009,7 +1115,7 @@ hipError_t launch_element(const DevView& v, bool nt, hipStream_t s)
 hipError_t launch_reduce_all(const DevView& v, const MapConfig& m, hipStream_t s)
 {
     const int64_t diag_lanes = ((int64_t)v.nd * 6 * m.qd + 63) / 64 * 64;
-    const int64_t threads = diag_lanes + (int64_t)v.no * 9 * m.qo;
+    const int64_t threads = diag_lanes + (m.qo == 1 ? ((int64_t)v.no + 6) / 7 * 64 : (int64_t)v.no * 9 * m.qo);
     if (v.nd + v.no == 0)
         return hipSuccess;
 #define LAUNCH(QD, QO)                                                                                    \
