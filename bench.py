@@ -271,7 +271,7 @@ class Stream:
             ev[1].synchronize()
             return ev[0].elapsed_time(ev[1]) * 1e3
 
-        rows, t_stream, t_cold, t_reb = [], [], [], []
+        rows, t_stream, t_cold, t_reb, t_reb_cold = [], [], [], [], []
         for k, ((di, ds), st) in enumerate(zip(self.dframes, self.stats)):
             ids_h = self.frames_host[k][0]
             prev = torch.from_numpy(self.mask_before(k)[ids_h].copy()).cuda()  # undoes the frame
@@ -281,17 +281,21 @@ class Stream:
                 (cold if c else warm).append(timed(lambda: asm.apply_edits(di, ds), c))
                 asm.apply_edits(di, prev)
             asm.apply_edits(di, ds)
-            reb = [timed(asm.full_rebuild, r % 2 == 1) for r in range(max(4, reps // 2))]
+            nreb = max(4, reps // 2)
+            reb = [timed(asm.full_rebuild, False) for _ in range(nreb)]
+            reb_cold = [timed(asm.full_rebuild, True) for _ in range(nreb // 2)]
             alg = bytes_frame(st)
             rows.append({"frame": k, "edits": st["edits"], "touched_blocks": st["touched_blocks"],
                          "touched_slots": st["touched_slots"], "stream_us": round(float(np.median(warm)), 3),
                          "stream_cold_us": round(float(np.median(cold)), 3) if cold else None,
-                         "rebuild_us": round(float(np.median(reb)), 3), "alg_bytes": alg,
+                         "rebuild_us": round(float(np.median(reb)), 3),
+                         "rebuild_cold_us": round(float(np.median(reb_cold)), 3), "alg_bytes": alg,
                          "stream_gbs": round(alg / (np.median(warm) * 1e-6) / 1e9, 2)})
             t_stream.append(float(np.median(warm)))
             if cold:
                 t_cold.append(float(np.median(cold)))
             t_reb.append(float(np.median(reb)))
+            t_reb_cold.append(float(np.median(reb_cold)))
         del flush
         ratio = np.asarray(t_reb) / np.asarray(t_stream)
         peak = int(np.argmax([r["edits"] for r in rows]))
@@ -304,6 +308,7 @@ class Stream:
                                     "max": round(float(np.max(t_stream)), 3)},
             "stream_cold_us_per_frame": summ(t_cold) if t_cold else None,
             "rebuild_us": summ(t_reb),
+            "rebuild_cold_us": summ(t_reb_cold),
             "stream_vs_rebuild": {"median_ratio": round(float(np.median(ratio)), 2),
                                   "min_ratio": round(float(np.min(ratio)), 2), "peak_frame": peak,
                                   "peak_frame_ratio": round(float(ratio[peak]), 2)},
@@ -722,6 +727,7 @@ def main():
         del src, dst
     if not args.quick:
         out["latency_floor"] = stafem.latency_probe()
+        out["hbm_measured"] = {k: round(x, 1) for k, x in stafem.bandwidth_probe().items()}
         out["roofline_rebuild"] = s.rebuild_roofline()
         out.update(s.per_frame(args.reps))
         out["stream_vs_rebuild"]["pipelined_ratio"] = round(

@@ -300,6 +300,15 @@ sta_status sta_batch_offsets(const sta_ctx* ctx, int* k, int64_t* node_off, int6
  * dependent round trips each, so these numbers bound its latency. */
 sta_status sta_latency_probe(void* stream, double* out4);
 
+/* Measured streaming bandwidth of this GPU's HBM, in GB/s (1e9 B/s), on
+ * `stream`: out3[0] reading 1 GiB, out3[1] writing 1 GiB, out3[2] copying
+ * 1 GiB (2 GiB moved), 16-byte accesses by consecutive lanes, averaged over
+ * ten launches after one warm-up.  Allocates and frees 2 GiB of device
+ * memory; synchronises `stream`.  The achieved fractions of the rebuild
+ * kernels are reported against the published 8 TB/s peak; these numbers
+ * say what a plain streaming kernel reaches on the same device. */
+sta_status sta_bandwidth_probe(void* stream, double* out3);
+
 /* Synchronise `stream`, return and clear the first error the device
  * recorded (STA_ERANGE, STA_EDUP, STA_EDEGENERATE), else STA_OK. */
 sta_status sta_status_sync(sta_ctx* ctx, void* stream);

@@ -54,6 +54,34 @@ __global__ void k_atomic_chain(uint32_t* __restrict__ chase, int hops, uint64_t*
 
 __global__ void k_empty() {}
 
+// Streaming bandwidth kernels: 16-byte accesses, consecutive lanes on
+// consecutive addresses, grid-stride over the buffer.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+__global__ __launch_bounds__(256) void k_bw_read(const dvec2* __restrict__ src, int64_t n, double* out)
+{
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const dvec2 x = src[i];
+        acc += x.x + x.y;
+    }
+    if (acc == -1.0)  // never true for the positive fill; keeps the loads live
+        out[0] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_bw_write(dvec2* __restrict__ dst, int64_t n)
+{
+    const dvec2 one = {1.0, 1.0};
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        dst[i] = one;
+}
+
+__global__ __launch_bounds__(256) void k_bw_copy(const dvec2* __restrict__ src, dvec2* __restrict__ dst, int64_t n)
+{
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        dst[i] = src[i];
+}
+
 }  // namespace
 
 }  // namespace sta
@@ -130,5 +158,58 @@ extern "C" sta_status sta_latency_probe(void* stream, double* out4)
         return STA_EHIP;
     for (int k = 0; k < 4; ++k)
         out4[k] = res[k];
+    return STA_OK;
+}
+
+extern "C" sta_status sta_bandwidth_probe(void* stream, double* out3)
+{
+    if (!out3)
+        return STA_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t bytes = 1ll << 30;  // per buffer, far beyond the 256 MB Infinity Cache
+    const int64_t n = bytes / 16;
+    const unsigned grid = 8192;
+    const int reps = 10;
+    dvec2 *a = nullptr, *b = nullptr;
+    double* dout = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&a, bytes);
+    if (e == hipSuccess) e = hipMalloc(&b, bytes);
+    if (e == hipSuccess) e = hipMalloc(&dout, sizeof(double));
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    double res[3] = {0, 0, 0};
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_bw_write, dim3(grid), dim3(256), 0, s, a, n);
+        hipLaunchKernelGGL(k_bw_write, dim3(grid), dim3(256), 0, s, b, n);
+        e = hipGetLastError();
+    }
+    for (int which = 0; which < 3 && e == hipSuccess; ++which) {
+        for (int r = -1; r < reps && e == hipSuccess; ++r) {  // r = -1: warm-up
+            if (r == 0) e = hipEventRecord(e0, s);
+            if (which == 0)
+                hipLaunchKernelGGL(k_bw_read, dim3(grid), dim3(256), 0, s, a, n, dout);
+            else if (which == 1)
+                hipLaunchKernelGGL(k_bw_write, dim3(grid), dim3(256), 0, s, b, n);
+            else
+                hipLaunchKernelGGL(k_bw_copy, dim3(grid), dim3(256), 0, s, a, b, n);
+            if (e == hipSuccess) e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        const double moved = (double)bytes * (which == 2 ? 2 : 1) * reps;
+        res[which] = moved / (ms * 1e-3) / 1e9;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    if (dout) (void)hipFree(dout);
+    if (e != hipSuccess)
+        return STA_EHIP;
+    for (int k = 0; k < 3; ++k)
+        out3[k] = res[k];
     return STA_OK;
 }

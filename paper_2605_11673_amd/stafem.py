@@ -67,6 +67,7 @@ SIGNATURES = {
     "sta_batch_build": (_int, [_int, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _dbl, _vp, _vp, ctypes.POINTER(_vp)]),
     "sta_batch_offsets": (_int, [_vp, ctypes.POINTER(_int), _vp, _vp, _vp, _vp, _i64]),
     "sta_latency_probe": (_int, [_vp, ctypes.POINTER(_dbl)]),
+    "sta_bandwidth_probe": (_int, [_vp, ctypes.POINTER(_dbl)]),
     "sta_status_sync": (_int, [_vp, _vp]),
     "sta_last_error": (ctypes.c_char_p, [_vp]),
     "sta_destroy": (None, [_vp]),
@@ -488,6 +489,13 @@ class Proxy:
     def last_error(self) -> str:
         m = load().sta_proxy_last_error(self._p)
         return m.decode() if m else ""
+
+
+def bandwidth_probe(stream=None) -> dict:
+    """Measured HBM streaming bandwidth in GB/s (see sta_bandwidth_probe)."""
+    out = (ctypes.c_double * 3)()
+    _check(load().sta_bandwidth_probe(_stream_handle(stream), out), None)
+    return {"read_GBs": out[0], "write_GBs": out[1], "copy_GBs": out[2]}
 
 
 def latency_probe(stream=None) -> dict:
