@@ -154,7 +154,9 @@ class Stream:
     def tune(self, peak):
         di, ds = self.dframes[peak]
         rep = self.asm.autotune(di, ds, reps=7)
-        return self.asm.get_config(), [r for r in rep.splitlines() if r.strip()]
+        cfg = self.asm.get_config()
+        cfg["buckets"] = {k: self.asm.bucket_map(k) for k in ("rebuild", "stream")}
+        return cfg, [r for r in rep.splitlines() if r.strip()]
 
     def stats_pass(self, check_parity):
         torch, asm = self.torch, self.asm
@@ -503,13 +505,20 @@ def drift(torch, asm):
             "entries": int(ref.numel())}
 
 
+def apply_config(asm, cfg):
+    """The tuned configuration of the headline context, bucket maps included."""
+    asm.set_config(*[cfg[k] for k in ("fused", "rebuild_qd", "rebuild_qo", "stream_qd", "stream_qo", "grid_cap",
+                                      "rebuild_nt")])
+    for k, m in cfg.get("buckets", {}).items():
+        asm.set_bucket_map(k, m["diag"], m["off"])
+
+
 def delta_section(torch, stafem, w, frames, cfg, exact_step_s, args):
     """The paper's +/- delta policy (sta_apply_edits_delta) on the headline stream and on a
     repeated-locality stream (one slab deleted and reinserted frame after frame): time per
     frame against the exact policy, and the drift from the rebuild after many frames."""
     asm = stafem.Assembler.from_workload(w)
-    asm.set_config(*[cfg[k] for k in ("fused", "rebuild_qd", "rebuild_qo", "stream_qd", "stream_qo", "grid_cap",
-                                      "rebuild_nt")])
+    apply_config(asm, cfg)
     dfr = [stafem.upload_frame(ids, st) for ids, st in frames]
 
     def delta_step():
@@ -565,7 +574,6 @@ def euler_section(torch, stafem, workloads, w, frames, cfg, args, rtol=1e-8):
     """Implicit-Euler loop of eq. (9) over the headline stream (one time step per frame,
     gravity plus a surface load, from rest): each policy's matrix update and the solve,
     timed per frame; the two policies' trajectories must agree bit for bit."""
-    keys = ("fused", "rebuild_qd", "rebuild_qo", "stream_qd", "stream_qo", "grid_cap", "rebuild_nt")
     f = torch.from_numpy(workloads.loads_for(w, w.mask0).reshape(-1)).cuda()
     dfr = [stafem.upload_frame(ids, st) for ids, st in frames]
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
@@ -573,7 +581,7 @@ def euler_section(torch, stafem, workloads, w, frames, cfg, args, rtol=1e-8):
     traj = {}
     for policy in ("stream", "rebuild"):
         asm = stafem.Assembler.from_workload(w)
-        asm.set_config(*[cfg[k] for k in keys])
+        apply_config(asm, cfg)
         u = torch.zeros(asm.n_rows, dtype=torch.float64, device="cuda")
         v = torch.zeros_like(u)
         upd, sol, its = [], [], []
@@ -706,7 +714,8 @@ def main():
                                "24 Voronoi fracture frames + 24 reinsertion frames, FP64",
                    "n_tets": w.n_tets, "n_nodes": w.n_nodes, "nnz": asm.nnz, "frames_per_step": len(frames),
                    "edits_per_step": edits_per_step, "touched_slots_per_step": slots_per_step, "seed": args.seed},
-        "tuned_config": asm.get_config(),
+        "tuned_config": {**asm.get_config(),
+                         "buckets": {k: asm.bucket_map(k) for k in ("rebuild", "stream")}},
         "timing_mode": "whole step captured as one HIP graph, replayed",
         "host_launched": {"ms_per_step": eager_s * 1e3, "value": slots_per_step / eager_s},
         "stream_pipelined_us_per_frame": round(step_s * 1e6 / len(frames), 3),

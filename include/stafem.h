@@ -253,8 +253,9 @@ sta_status sta_components(sta_ctx* ctx, int32_t* labels_dev, int64_t* n_componen
  *               cooperating on one block value for diagonal / off-diagonal
  *               blocks in the rebuild and in the streaming update
  *               (diagonal: 1 = thread-, 4 = quad-, 16 = wave-sixteenth-per-slot;
- *               off-diagonal: 1 or 4).  Every mapping adds the same terms in
- *               the same order: results are bit-identical.
+ *               off-diagonal: 1 or 4), here for every incidence-length
+ *               bucket alike (see sta_set_bucket_map).  Every mapping adds the
+ *               same terms in the same order: results are bit-identical.
  *   grid_cap    upper bound on the fused kernel's workgroups (0 = the
  *               co-resident limit).
  *   rebuild_nt  1: the rebuild streams contributions and values with
@@ -264,11 +265,33 @@ sta_status sta_set_config(sta_ctx* ctx, int fused, int rebuild_qd, int rebuild_q
                           int grid_cap, int rebuild_nt);
 sta_status sta_get_config(const sta_ctx* ctx, int* out7);
 
+/* Slot mapping per incidence-length bucket.  A block's incidence length
+ * kappa is the number of candidate tets in its segment (paper Sec. 3.3:
+ * the per-block work of a local recompute, O(|Delta| kappa) in Prop. 1).
+ * Diagonal blocks fall in bucket 0 (kappa <= 8), 1 (9..32) or 2 (> 32);
+ * off-diagonal blocks in bucket 0 (kappa <= 8) or 1 (> 8).  qd3[b] in
+ * {1, 4, 16} and qo2[b] in {1, 4} give the lanes per value for each bucket;
+ * which = 0 sets the rebuild's mapping, 1 the streaming update's.  The
+ * kernels allocate the largest group per block and a block of a bucket with
+ * a smaller group leaves the rest idle, so a mixed mapping trades idle lanes
+ * for load depth where segment lengths differ; sta_autotune chooses it by
+ * timing.  sta_set_config resets every bucket to one mapping.  Results are
+ * bit-identical for every mapping.  sta_get_config reports the allocation
+ * (the largest group).  STA_EINVAL on a value outside the sets above. */
+sta_status sta_set_bucket_map(sta_ctx* ctx, int which, const int* qd3, const int* qo2);
+
+/* The mapping per bucket (qd3, qo2; either may be NULL) and the number of
+ * blocks in each bucket (blocks5: 3 diagonal then 2 off-diagonal counts;
+ * may be NULL). */
+sta_status sta_get_bucket_map(const sta_ctx* ctx, int which, int* qd3, int* qo2, int64_t* blocks5);
+
 /* Autotuner: times every slot mapping for the full rebuild, and every
  * mapping x {two launches, fused with grid caps} for one streaming frame
  * (ids_dev / states_dev, device, n_edits; each timed application is undone
- * before the next), keeps the fastest of each, and returns a text report in
- * report (may be NULL).  If the environment variable STA_TUNE_CACHE names a
+ * before the next), keeps the fastest of each, then, for every non-empty
+ * incidence-length bucket in turn, tries each group size for that bucket
+ * alone (sta_set_bucket_map) and keeps it where it is faster, and returns a
+ * text report in report (may be NULL).  If the environment variable STA_TUNE_CACHE names a
  * file, a previous result for the same mesh sizes and frame size is reused
  * from it and new results are appended.  Synchronises `stream`. */
 sta_status sta_autotune(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* states_dev, int64_t n_edits,

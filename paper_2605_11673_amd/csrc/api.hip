@@ -193,6 +193,10 @@ sta_status build_context(const double* x, int64_t n_nodes, const int32_t* tets, 
     c->nnz = P.nnz;
     c->nd = P.nd;
     c->no = P.no;
+    for (int64_t b = 0; b < P.nd; ++b)
+        c->bucket_blocks[diag_bucket(P.dseg[b + 1] - P.dseg[b])]++;
+    for (int64_t o = 0; o < P.no; ++o)
+        c->bucket_blocks[kDiagBuckets + off_bucket(P.oseg[o + 1] - P.oseg[o])]++;
     c->nu = nu;
     c->rho = rho;
     c->dt = dt;
@@ -657,11 +661,10 @@ sta_status sta_set_config(sta_ctx* ctx, int fused, int rebuild_qd, int rebuild_q
     if (!ctx || (fused != 0 && fused != 1) || !valid_map(rebuild_qd, rebuild_qo) || !valid_map(stream_qd, stream_qo) ||
         grid_cap < 0 || (rebuild_nt != 0 && rebuild_nt != 1))
         return STA_EINVAL;
-    if (stream_qd != ctx->stream_map.qd || stream_qo != ctx->stream_map.qo)
-        ctx->frame_max_grid = 0;
+    ctx->frame_max_grid = 0;  // the fused kernel's occupancy depends on the mapping
     ctx->fused = fused;
-    ctx->rebuild_map = MapConfig{rebuild_qd, rebuild_qo, rebuild_nt};
-    ctx->stream_map = MapConfig{stream_qd, stream_qo, 0};
+    ctx->rebuild_map = uniform_map(rebuild_qd, rebuild_qo, rebuild_nt);
+    ctx->stream_map = uniform_map(stream_qd, stream_qo, 0);
     ctx->frame_grid_cap = grid_cap;
     return STA_OK;
 }
@@ -678,6 +681,48 @@ sta_status sta_get_config(const sta_ctx* ctx, int* out7)
     out6[4] = ctx->stream_map.qo;
     out6[5] = ctx->frame_grid_cap;
     out6[6] = ctx->rebuild_map.nt;
+    return STA_OK;
+}
+
+sta_status sta_set_bucket_map(sta_ctx* ctx, int which, const int* qd3, const int* qo2)
+{
+    if (!ctx || (which != 0 && which != 1) || !qd3 || !qo2)
+        return STA_EINVAL;
+    MapConfig m = which == 0 ? ctx->rebuild_map : ctx->stream_map;
+    m.qd = 1;
+    m.qo = 1;
+    for (int b = 0; b < kDiagBuckets; ++b) {
+        if (!valid_map(qd3[b], 1))
+            return STA_EINVAL;
+        m.qdb[b] = qd3[b];
+        m.qd = qd3[b] > m.qd ? qd3[b] : m.qd;
+    }
+    for (int b = 0; b < kOffBuckets; ++b) {
+        if (!valid_map(1, qo2[b]))
+            return STA_EINVAL;
+        m.qob[b] = qo2[b];
+        m.qo = qo2[b] > m.qo ? qo2[b] : m.qo;
+    }
+    if (which == 0) {
+        ctx->rebuild_map = m;
+    } else {
+        ctx->stream_map = m;
+        ctx->frame_max_grid = 0;
+    }
+    return STA_OK;
+}
+
+sta_status sta_get_bucket_map(const sta_ctx* ctx, int which, int* qd3, int* qo2, int64_t* blocks5)
+{
+    if (!ctx || (which != 0 && which != 1))
+        return STA_EINVAL;
+    const MapConfig& m = which == 0 ? ctx->rebuild_map : ctx->stream_map;
+    for (int b = 0; b < kDiagBuckets; ++b)
+        if (qd3) qd3[b] = m.qdb[b];
+    for (int b = 0; b < kOffBuckets; ++b)
+        if (qo2) qo2[b] = m.qob[b];
+    for (int b = 0; b < kDiagBuckets + kOffBuckets; ++b)
+        if (blocks5) blocks5[b] = ctx->bucket_blocks[b];
     return STA_OK;
 }
 

@@ -252,10 +252,12 @@ __device__ __forceinline__ double seg_sum(const double* __restrict__ c, int stri
     return acc;
 }
 
-// Terms held per lane per chunk: about 32 loads in flight per diagonal value.
+// Terms held per lane per chunk: about 32 loads in flight per diagonal value
+// (64 with sixteen lanes, so that the long segments of refinement supersets,
+// 48 tets, are read in one round).
 template <int Q>
 struct DiagChunk {
-    static constexpr int CH = Q == 1 ? 32 : (Q == 4 ? 8 : 2);
+    static constexpr int CH = Q == 1 ? 32 : (Q == 4 ? 8 : 4);
 };
 template <int Q>
 struct OffChunk {
@@ -287,6 +289,41 @@ __device__ __forceinline__ void block_value(const DevView& v, const BlockDesc& d
             st<NT>(v.values + d.lo + r * d.rlj + p, acc);
         }
     }
+}
+
+// block_value with the lane group size Q of the block's incidence-length
+// bucket (Q <= the allocation QD / QO; a power of four, so that groups
+// aligned to Q never straddle a wave).  MIXED = false: every bucket uses the
+// allocation, and only that code path is compiled (the smaller mappings'
+// deeper load chunks would otherwise cost registers and occupancy).
+template <int QD, int QO, bool MIXED, bool NT = false>
+__device__ __forceinline__ void block_value_q(const DevView& v, const BlockDesc& d, int vi, int q, int src0, int Q)
+{
+    if (!MIXED) {
+        block_value<QD, QO, NT>(v, d, vi, q, src0);
+    } else if (d.kind == 0) {
+        if (QD >= 16 && Q == 16)
+            block_value<16, 1, NT>(v, d, vi, q, src0);
+        else if (QD >= 4 && Q == 4)
+            block_value<4, 1, NT>(v, d, vi, q, src0);
+        else
+            block_value<1, 1, NT>(v, d, vi, q, src0);
+    } else {
+        if (QO >= 4 && Q == 4)
+            block_value<1, 4, NT>(v, d, vi, q, src0);
+        else
+            block_value<1, 1, NT>(v, d, vi, q, src0);
+    }
+}
+
+// Lane group size of block d under mapping m (its incidence-length bucket's).
+template <int QD, int QO, bool MIXED>
+__device__ __forceinline__ int bucket_q(const MapConfig& m, const BlockDesc& d)
+{
+    if (!MIXED)
+        return d.kind == 0 ? QD : QO;
+    const int kappa = d.k1 - d.k0;
+    return d.kind == 0 ? m.qdb[diag_bucket(kappa)] : m.qob[off_bucket(kappa)];
 }
 
 __device__ __forceinline__ BlockDesc load_desc(const BlockDesc* p)
@@ -434,8 +471,10 @@ __device__ __forceinline__ void off_value_rows(const DevView& v, const BlockDesc
 // Lanes: 6*QD per diagonal block (section padded to whole waves), then the
 // off-diagonal blocks: for QO = 1, 7 blocks of 9 lanes per wave (lane 63
 // idle, so that a block never straddles two waves), else 9*QO per block.
-template <int QD, int QO, bool NT>
-__global__ __launch_bounds__(kBlock) void k_reduce_all(DevView v, int64_t diag_lanes)
+// Each block's lanes use its incidence-length bucket's group size Q (at most
+// the allocation); lanes past 6Q (9Q) of a block idle.
+template <int QD, int QO, bool MIXED, bool NT>
+__global__ __launch_bounds__(kBlock) void k_reduce_all(DevView v, int64_t diag_lanes, MapConfig m)
 {
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t t = (int64_t)wg * kBlock + threadIdx.x;
@@ -445,8 +484,12 @@ __global__ __launch_bounds__(kBlock) void k_reduce_all(DevView v, int64_t diag_l
         if (b >= v.nd)
             return;
         const int rem = (int)(t - (int64_t)b * (6 * QD));
-        const int q = rem % QD;
-        block_value<QD, QO, NT>(v, load_desc(v.desc + b), rem / QD, q, lane - q);
+        const BlockDesc d = load_desc(v.desc + b);
+        const int Q = bucket_q<QD, QO, MIXED>(m, d);
+        if (rem >= 6 * Q)
+            return;
+        const int q = rem & (Q - 1);
+        block_value_q<QD, QO, MIXED, NT>(v, d, rem / Q, q, lane - q, Q);
     } else {
         const int64_t u = t - diag_lanes;
         if (QO == 1) {
@@ -461,8 +504,12 @@ __global__ __launch_bounds__(kBlock) void k_reduce_all(DevView v, int64_t diag_l
         if (o >= v.no)
             return;
         const int rem = (int)(u - (int64_t)o * (9 * QO));
-        const int q = rem % QO;
-        block_value<QD, QO, NT>(v, load_desc(v.desc + v.nd + o), rem / QO, q, lane - q);
+        const BlockDesc d = load_desc(v.desc + v.nd + o);
+        const int Q = bucket_q<QD, QO, MIXED>(m, d);
+        if (rem >= 9 * Q)
+            return;
+        const int q = rem & (Q - 1);
+        block_value_q<QD, QO, MIXED, NT>(v, d, rem / Q, q, lane - q, Q);
     }
 }
 
@@ -666,51 +713,53 @@ struct Phase2 {
     static constexpr int kRegionLanes = (kDiagLanes + kRegionOff * LO + 63) / 64 * 64;
 };
 
-// Decode phase-2 lane t: a record lane (region w, slot in the region, value
-// vi, place q in the value's lane group), an edit lane (edit = index into
-// the edit list, returned in w with slot = -1) or a padding lane (slot = -2).
+// Decode phase-2 lane t: a record lane (region w, slot in the region, lane
+// rem among the record's 6 QD or 9 QO lanes), an edit lane (edit = index
+// into the edit list, returned in w with slot = -1) or a padding lane
+// (slot = -2).
 template <int QD, int QO>
-__device__ __forceinline__ void touched_role(int64_t t, int regions, int& w, int& slot, int& vi, int& q)
+__device__ __forceinline__ void touched_role(int64_t t, int regions, int& w, int& slot, int& rem)
 {
     using P = Phase2<QD, QO>;
     const int64_t rl = (int64_t)regions * P::kRegionLanes;
+    rem = 0;
     if (t >= rl) {
         w = (int)(t - rl);
         slot = -1;
-        vi = q = 0;
         return;
     }
     w = (int)(t / P::kRegionLanes);
     const int u = (int)(t - (int64_t)w * P::kRegionLanes);
     if (u < P::kDiagLanes) {
         slot = u / P::LD;
-        const int rem = u - slot * P::LD;
-        vi = rem / QD;
-        q = rem - vi * QD;
+        rem = u - slot * P::LD;
     } else {
         const int u2 = u - P::kDiagLanes;
         const int k = u2 / P::LO;
         if (k >= kRegionOff) {
             slot = -2;
-            vi = q = 0;
             return;
         }
         slot = kRegionDiag + k;
-        const int rem = u2 - k * P::LO;
-        vi = rem / QO;
-        q = rem - vi * QO;
+        rem = u2 - k * P::LO;
     }
 }
 
-// Phase 2, record lane: re-sum value vi of a claimed block (lane group of Q,
-// place q) unless the frame has an error; the first lane of the record
-// releases the block's claim stamp either way.
-template <int QD, int QO>
-__device__ __forceinline__ void touched_record(const DevView& v, const BlockDesc& d, int fe, int vi, int q)
+// Phase 2, record lane rem: re-sum value rem / Q of a claimed block, Q lanes
+// per value (Q from the block's incidence-length bucket; lanes past the
+// record's 6Q or 9Q idle) unless the frame has an error; the record's first
+// lane releases the block's claim stamp either way.
+template <int QD, int QO, bool MIXED>
+__device__ __forceinline__ void touched_record(const DevView& v, const BlockDesc& d, int fe, int rem,
+                                               const MapConfig& m)
 {
+    const int Q = bucket_q<QD, QO, MIXED>(m, d);
+    if (rem >= (d.kind == 0 ? 6 : 9) * Q)
+        return;
+    const int q = rem & (Q - 1);
     if (!fe)
-        block_value<QD, QO>(v, d, vi, q, (threadIdx.x & 63) - q);
-    if (vi == 0 && q == 0)
+        block_value_q<QD, QO, MIXED>(v, d, rem / Q, q, (threadIdx.x & 63) - q, Q);
+    if (rem == 0)
         v.bstamp[d.block] = 0u;
 }
 
@@ -815,16 +864,16 @@ __global__ __launch_bounds__(kBlock) void k_edits(DevView v, const int32_t* __re
 }
 
 // Phase 2 as its own kernel.
-template <int QD, int QO>
+template <int QD, int QO, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_touched(DevView v, const int32_t* __restrict__ ids, int32_t n_host,
-                                                    const int32_t* __restrict__ n_dev)
+                                                    const int32_t* __restrict__ n_dev, MapConfig m)
 {
     __shared__ int s_bits;
     // the edit phase ran `edit_wgs` workgroups of kRegionsPerBlock waves, each wave one claim region
     const int edit_wgs = n_host > 0 ? (n_host * kEditLanes + kBlock - 1) / kBlock : 1;
     const int regions = edit_wgs * kRegionsPerBlock;
-    int w, slot, vi, q;
-    touched_role<QD, QO>((int64_t)blockIdx.x * kBlock + threadIdx.x, regions, w, slot, vi, q);
+    int w, slot, rem;
+    touched_role<QD, QO>((int64_t)blockIdx.x * kBlock + threadIdx.x, regions, w, slot, rem);
     // claim record and count, or the edit's id and undo byte, load together
     // with the error bytes and the device-side count; lanes without them read
     // fixed empty values instead, so the loads need no branch
@@ -844,7 +893,7 @@ __global__ __launch_bounds__(kBlock) void k_touched(DevView v, const int32_t* __
     publish_frame(v, fe, n, regions);
     if (rec_lane) {
         if (slot - (slot >= kRegionDiag ? kRegionDiag : 0) < cnt)
-            touched_record<QD, QO>(v, d, fe, vi, q);
+            touched_record<QD, QO, MIXED>(v, d, fe, rem, m);
     } else if (edit_lane_ && w < n) {
         touched_edit(v, id, u, fe);
     }
@@ -1019,10 +1068,10 @@ __device__ __forceinline__ bool grid_barrier(Ctl* ctl, unsigned G, int* s_ok)
 // The whole frame in one persistent launch: phase 1 over the edits, grid
 // barrier, phase 2 over the claimed blocks (grid-stride loops; lane groups
 // stay aligned because the stride is a multiple of the workgroup size).
-template <int QD, int QO>
+template <int QD, int QO, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_frame(DevView v, const int32_t* __restrict__ ids,
                                                   const uint8_t* __restrict__ states, int32_t n_host,
-                                                  const int32_t* __restrict__ n_dev)
+                                                  const int32_t* __restrict__ n_dev, MapConfig m)
 {
     __shared__ int s_bits;
     __shared__ int s_ok;
@@ -1050,12 +1099,12 @@ __global__ __launch_bounds__(kBlock) void k_frame(DevView v, const int32_t* __re
     publish_frame(v, fe, n, regions);
     const int64_t total = (int64_t)regions * Phase2<QD, QO>::kRegionLanes + n_host;
     for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total; t += (int64_t)gridDim.x * kBlock) {
-        int w, slot, vi, q;
-        touched_role<QD, QO>(t, regions, w, slot, vi, q);
+        int w, slot, rem;
+        touched_role<QD, QO>(t, regions, w, slot, rem);
         if (slot >= 0) {
             const int c = v.rcount[2 * w + (slot >= kRegionDiag ? 1 : 0)];
             if (slot - (slot >= kRegionDiag ? kRegionDiag : 0) < c)
-                touched_record<QD, QO>(v, load_desc(v.rec + (size_t)w * kRegion + slot), fe, vi, q);
+                touched_record<QD, QO, MIXED>(v, load_desc(v.rec + (size_t)w * kRegion + slot), fe, rem, m);
         } else if (slot == -1 && w < n) {
             touched_edit(v, ids[w], v.undo[w], fe);
         }
@@ -1112,20 +1161,36 @@ hipError_t launch_element(const DevView& v, bool nt, hipStream_t s)
 
 #define STA_MAPPINGS(X) X(1, 1) X(1, 4) X(4, 1) X(4, 4) X(16, 1) X(16, 4)
 
+// Whether some incidence-length bucket uses fewer lanes than the allocation.
+bool mixed_map(const MapConfig& m)
+{
+    for (int b = 0; b < kDiagBuckets; ++b)
+        if (m.qdb[b] != m.qd)
+            return true;
+    for (int b = 0; b < kOffBuckets; ++b)
+        if (m.qob[b] != m.qo)
+            return true;
+    return false;
+}
+
 hipError_t launch_reduce_all(const DevView& v, const MapConfig& m, hipStream_t s)
 {
     const int64_t diag_lanes = ((int64_t)v.nd * 6 * m.qd + 63) / 64 * 64;
     const int64_t threads = diag_lanes + (m.qo == 1 ? ((int64_t)v.no + 6) / 7 * 64 : (int64_t)v.no * 9 * m.qo);
     if (v.nd + v.no == 0)
         return hipSuccess;
+    const bool mixed = mixed_map(m);
 #define LAUNCH(QD, QO)                                                                                    \
     if (m.qd == QD && m.qo == QO) {                                                                       \
-        if (m.nt)                                                                                         \
-            launch_kernel(&k_reduce_all<QD, QO, true>, dim3(blocks_for(threads)), dim3(kBlock), 0, s, v, \
-                               diag_lanes);                                                               \
+        const dim3 g(blocks_for(threads));                                                                \
+        if (mixed && m.nt)                                                                                \
+            launch_kernel(&k_reduce_all<QD, QO, true, true>, g, dim3(kBlock), 0, s, v, diag_lanes, m);    \
+        else if (mixed)                                                                                   \
+            launch_kernel(&k_reduce_all<QD, QO, true, false>, g, dim3(kBlock), 0, s, v, diag_lanes, m);   \
+        else if (m.nt)                                                                                    \
+            launch_kernel(&k_reduce_all<QD, QO, false, true>, g, dim3(kBlock), 0, s, v, diag_lanes, m);   \
         else                                                                                              \
-            launch_kernel(&k_reduce_all<QD, QO, false>, dim3(blocks_for(threads)), dim3(kBlock), 0, s, v, \
-                               diag_lanes);                                                               \
+            launch_kernel(&k_reduce_all<QD, QO, false, false>, g, dim3(kBlock), 0, s, v, diag_lanes, m);  \
         return hipGetLastError();                                                                         \
     }
     STA_MAPPINGS(LAUNCH)
@@ -1161,8 +1226,12 @@ hipError_t launch_touched_phase(const DevView& v, const MapConfig& m, const int3
     if (m.qd == QD && m.qo == QO) {                                                                         \
         const int64_t regions = (n_host > 0 ? ((int64_t)n_host * kEditLanes + kBlock - 1) / kBlock : 1) * kRegionsPerBlock; \
         const int64_t lanes = regions * Phase2<QD, QO>::kRegionLanes + n_host;                              \
-        launch_kernel(&k_touched<QD, QO>, dim3(blocks_for(lanes)), dim3(kBlock), 0, s, v,                 \
-                           ids, n_host, n_dev);                                                             \
+        if (mixed_map(m))                                                                                   \
+            launch_kernel(&k_touched<QD, QO, true>, dim3(blocks_for(lanes)), dim3(kBlock), 0, s, v, ids,    \
+                          n_host, n_dev, m);                                                                \
+        else                                                                                                \
+            launch_kernel(&k_touched<QD, QO, false>, dim3(blocks_for(lanes)), dim3(kBlock), 0, s, v, ids,   \
+                          n_host, n_dev, m);                                                                \
         return hipGetLastError();                                                                           \
     }
     STA_MAPPINGS(LAUNCH)
@@ -1178,7 +1247,9 @@ hipError_t frame_max_grid(const MapConfig& m, int device, int* max_grid)
         return e;
 #define OCC(QD, QO)                                                                                        \
     if (m.qd == QD && m.qo == QO)                                                                          \
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)&k_frame<QD, QO>, kBlock, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(                                                  \
+            &per_cu, mixed_map(m) ? (const void*)&k_frame<QD, QO, true> : (const void*)&k_frame<QD, QO, false>, \
+            kBlock, 0);
     STA_MAPPINGS(OCC)
 #undef OCC
     if (e != hipSuccess)
@@ -1208,7 +1279,12 @@ hipError_t launch_frame(const DevView& v, const MapConfig& m, int grid, const in
 {
 #define LAUNCH(QD, QO)                                                                                        \
     if (m.qd == QD && m.qo == QO) {                                                                           \
-        launch_kernel(&k_frame<QD, QO>, dim3(grid), dim3(kBlock), 0, s, v, ids, states, n_host, n_dev); \
+        if (mixed_map(m))                                                                                     \
+            launch_kernel(&k_frame<QD, QO, true>, dim3(grid), dim3(kBlock), 0, s, v, ids, states, n_host,     \
+                          n_dev, m);                                                                          \
+        else                                                                                                  \
+            launch_kernel(&k_frame<QD, QO, false>, dim3(grid), dim3(kBlock), 0, s, v, ids, states, n_host,    \
+                          n_dev, m);                                                                          \
         return hipGetLastError();                                                                             \
     }
     STA_MAPPINGS(LAUNCH)

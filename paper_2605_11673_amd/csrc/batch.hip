@@ -29,12 +29,82 @@ sta_status tune_fail(sta_ctx* ctx, sta_status code, const std::string& msg)
 
 struct Cfg {
     int fused, rqd, rqo, sqd, sqo, cap, nt;
+    int rdb[kDiagBuckets], rob[kOffBuckets];  // rebuild mapping per incidence-length bucket
+    int sdb[kDiagBuckets], sob[kOffBuckets];  // streaming mapping per bucket
 };
+
+constexpr int kCfgInts = 7 + 2 * (kDiagBuckets + kOffBuckets);
+
+void cfg_ints(const Cfg& c, int* x)
+{
+    const int head[7] = {c.fused, c.rqd, c.rqo, c.sqd, c.sqo, c.cap, c.nt};
+    int k = 0;
+    for (int v : head) x[k++] = v;
+    for (int v : c.rdb) x[k++] = v;
+    for (int v : c.rob) x[k++] = v;
+    for (int v : c.sdb) x[k++] = v;
+    for (int v : c.sob) x[k++] = v;
+}
+
+Cfg cfg_from(const int* x)
+{
+    Cfg c;
+    c.fused = x[0], c.rqd = x[1], c.rqo = x[2], c.sqd = x[3], c.sqo = x[4], c.cap = x[5], c.nt = x[6];
+    int k = 7;
+    for (int& v : c.rdb) v = x[k++];
+    for (int& v : c.rob) v = x[k++];
+    for (int& v : c.sdb) v = x[k++];
+    for (int& v : c.sob) v = x[k++];
+    return c;
+}
+
+// Uniform mappings: every bucket as the allocation.
+void set_uniform(Cfg& c)
+{
+    for (int& v : c.rdb) v = c.rqd;
+    for (int& v : c.rob) v = c.rqo;
+    for (int& v : c.sdb) v = c.sqd;
+    for (int& v : c.sob) v = c.sqo;
+}
+
+Cfg current(const sta_ctx* ctx)
+{
+    Cfg c{ctx->fused, ctx->rebuild_map.qd, ctx->rebuild_map.qo, ctx->stream_map.qd, ctx->stream_map.qo,
+          ctx->frame_grid_cap, ctx->rebuild_map.nt, {}, {}, {}, {}};
+    for (int b = 0; b < kDiagBuckets; ++b) {
+        c.rdb[b] = ctx->rebuild_map.qdb[b];
+        c.sdb[b] = ctx->stream_map.qdb[b];
+    }
+    for (int b = 0; b < kOffBuckets; ++b) {
+        c.rob[b] = ctx->rebuild_map.qob[b];
+        c.sob[b] = ctx->stream_map.qob[b];
+    }
+    return c;
+}
+
+sta_status apply(sta_ctx* ctx, const Cfg& c)
+{
+    sta_status st = sta_set_config(ctx, c.fused, c.rqd, c.rqo, c.sqd, c.sqo, c.cap, c.nt);
+    if (st == STA_OK)
+        st = sta_set_bucket_map(ctx, 0, c.rdb, c.rob);
+    if (st == STA_OK)
+        st = sta_set_bucket_map(ctx, 1, c.sdb, c.sob);
+    return st;
+}
+
+std::string describe(const Cfg& c)
+{
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "fused %d rebuild %dx%d nt %d [%d %d %d | %d %d] stream %dx%d cap %d [%d %d %d | %d %d]",
+                  c.fused, c.rqd, c.rqo, c.nt, c.rdb[0], c.rdb[1], c.rdb[2], c.rob[0], c.rob[1], c.sqd, c.sqo, c.cap,
+                  c.sdb[0], c.sdb[1], c.sdb[2], c.sob[0], c.sob[1]);
+    return buf;
+}
 
 std::string cache_key(const sta_ctx* ctx, int64_t n_edits)
 {
     char buf[256];
-    std::snprintf(buf, sizeof buf, "stafem-tune-v2 %lld %lld %lld %lld %lld %lld", (long long)ctx->n_nodes,
+    std::snprintf(buf, sizeof buf, "stafem-tune-v3 %lld %lld %lld %lld %lld %lld", (long long)ctx->n_nodes,
                   (long long)ctx->n_tets, (long long)ctx->nnz, (long long)ctx->nd, (long long)ctx->no,
                   (long long)n_edits);
     return buf;
@@ -54,10 +124,17 @@ bool cache_lookup(const char* path, const std::string& key, Cfg& c)
         std::string k(line, bar - line);
         while (!k.empty() && k.back() == ' ')
             k.pop_back();
-        Cfg t;
-        if (k == key && std::sscanf(bar + 1, "%d %d %d %d %d %d %d", &t.fused, &t.rqd, &t.rqo, &t.sqd, &t.sqo, &t.cap,
-                                    &t.nt) == 7) {
-            c = t;  // the last matching line wins
+        if (k != key)
+            continue;
+        int x[kCfgInts];
+        int n = 0, used = 0;
+        const char* p = bar + 1;
+        while (n < kCfgInts && std::sscanf(p, "%d%n", &x[n], &used) == 1) {
+            p += used;
+            ++n;
+        }
+        if (n == kCfgInts) {
+            c = cfg_from(x);  // the last matching line wins
             found = true;
         }
     }
@@ -70,7 +147,12 @@ void cache_store(const char* path, const std::string& key, const Cfg& c)
     FILE* f = std::fopen(path, "a");
     if (!f)
         return;
-    std::fprintf(f, "%s | %d %d %d %d %d %d %d\n", key.c_str(), c.fused, c.rqd, c.rqo, c.sqd, c.sqo, c.cap, c.nt);
+    int x[kCfgInts];
+    cfg_ints(c, x);
+    std::fprintf(f, "%s |", key.c_str());
+    for (int v : x)
+        std::fprintf(f, " %d", v);
+    std::fprintf(f, "\n");
     std::fclose(f);
 }
 
@@ -149,7 +231,7 @@ sta_status sta_autotune(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* sta
         reps = 7;
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::string rep;
-    char line[256];
+    char line[320];
     const char* cache = std::getenv("STA_TUNE_CACHE");
     const std::string key = cache_key(ctx, n_edits);
     Cfg best{};
@@ -161,9 +243,8 @@ sta_status sta_autotune(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* sta
         return st;
     };
     if (cache && cache_lookup(cache, key, best)) {
-        sta_status st = sta_set_config(ctx, best.fused, best.rqd, best.rqo, best.sqd, best.sqo, best.cap, best.nt);
-        std::snprintf(line, sizeof line, "cached %s: fused %d rebuild %dx%d nt %d stream %dx%d cap %d\n", cache,
-                      best.fused, best.rqd, best.rqo, best.nt, best.sqd, best.sqo, best.cap);
+        const sta_status st = apply(ctx, best);
+        std::snprintf(line, sizeof line, "cached %s: %s\n", cache, describe(best).c_str());
         rep += line;
         return finish(st);
     }
@@ -208,19 +289,17 @@ sta_status sta_autotune(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* sta
         cleanup();
         return tune_fail(ctx, STA_ENOMEM, "autotune workspace");
     }
-    const Cfg saved{ctx->fused, ctx->rebuild_map.qd, ctx->rebuild_map.qo, ctx->stream_map.qd, ctx->stream_map.qo,
-                    ctx->frame_grid_cap, ctx->rebuild_map.nt};
+    const Cfg saved = current(ctx);
     const int saved_timing = ctx->timing;
     ctx->timing = false;
     sta_status st = STA_OK;
 
-    // 1. rebuild mapping
-    double best_t = 1e30;
-    best = saved;
-    for (int nt = 0; nt <= 1; ++nt)
-    for (auto& m : kMaps) {
-        sta_set_config(ctx, saved.fused, m[0], m[1], saved.sqd, saved.sqo, saved.cap, nt);
+    // median time of one rebuild / of one streaming frame (each undone by
+    // its inverse) under configuration c, in microseconds
+    auto time_rebuild = [&](const Cfg& c) {
         std::vector<float> t;
+        if (st == STA_OK)
+            st = apply(ctx, c);
         for (int r = 0; r <= reps && st == STA_OK; ++r) {
             float ms = 0.0f;
             (void)hipEventRecord(a, s);
@@ -231,38 +310,98 @@ sta_status sta_autotune(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* sta
             if (r > 0)
                 t.push_back(ms);
         }
-        const double med = median(t) * 1e3;
-        std::snprintf(line, sizeof line, "rebuild  map %2dx%d nt %d: %9.2f us\n", m[0], m[1], nt, med);
-        rep += line;
-        if (med < best_t) {
-            best_t = med;
-            best.rqd = m[0];
-            best.rqo = m[1];
-            best.nt = nt;
+        return median(t) * 1e3;
+    };
+    auto time_frame = [&](const Cfg& c) {
+        std::vector<float> t;
+        if (st == STA_OK)
+            st = apply(ctx, c);
+        for (int r = 0; r <= reps && st == STA_OK; ++r) {
+            float ms = 0.0f;
+            (void)hipEventRecord(a, s);
+            st = sta_apply_edits(ctx, ids_dev, states_dev, n_edits, stream);
+            (void)hipEventRecord(b, s);
+            if (st == STA_OK)
+                st = sta_apply_edits(ctx, ids_dev, inv_dev, n_edits, stream);
+            (void)hipEventSynchronize(b);
+            (void)hipEventElapsedTime(&ms, a, b);
+            if (r > 0)
+                t.push_back(ms);
         }
-    }
+        return median(t) * 1e3;
+    };
+    // one bucket at a time, each group size of that bucket alone; a change
+    // is kept only if it is at least 1% faster
+    auto refine = [&](Cfg& c, double& t_best, bool rebuild) {
+        const char* what = rebuild ? "rebuild" : "frame  ";
+        for (int bk = 0; bk < kDiagBuckets + kOffBuckets && st == STA_OK; ++bk) {
+            if (ctx->bucket_blocks[bk] == 0)
+                continue;
+            const bool diag = bk < kDiagBuckets;
+            const int nq = diag ? 3 : 2;
+            const int qs[3] = {1, 4, 16};
+            int* slot = diag ? (rebuild ? &c.rdb[bk] : &c.sdb[bk])
+                             : (rebuild ? &c.rob[bk - kDiagBuckets] : &c.sob[bk - kDiagBuckets]);
+            const int keep = *slot;
+            int chosen = keep;
+            for (int k = 0; k < nq && st == STA_OK; ++k) {
+                if (qs[k] == keep)
+                    continue;
+                *slot = qs[k];
+                const double t = rebuild ? time_rebuild(c) : time_frame(c);
+                std::snprintf(line, sizeof line, "%s  bucket %s%d (%lld blocks) q %2d: %9.2f us\n", what,
+                              diag ? "d" : "o", diag ? bk : bk - kDiagBuckets, (long long)ctx->bucket_blocks[bk],
+                              qs[k], t);
+                rep += line;
+                if (t < 0.99 * t_best) {
+                    t_best = t;
+                    chosen = qs[k];
+                }
+            }
+            *slot = chosen;
+        }
+    };
 
-    // 2. streaming frame: mapping x mode
+    // 1. rebuild: uniform mappings, then per bucket
+    double best_t = 1e30;
+    best = saved;
+    for (int nt = 0; nt <= 1 && st == STA_OK; ++nt)
+        for (auto& m : kMaps) {
+            Cfg c = saved;
+            c.rqd = m[0], c.rqo = m[1], c.nt = nt;
+            set_uniform(c);
+            const double med = time_rebuild(c);
+            std::snprintf(line, sizeof line, "rebuild  map %2dx%d nt %d: %9.2f us\n", m[0], m[1], nt, med);
+            rep += line;
+            if (med < best_t) {
+                best_t = med;
+                best.rqd = m[0];
+                best.rqo = m[1];
+                best.nt = nt;
+            }
+        }
+    for (int bk = 0; bk < kDiagBuckets; ++bk)
+        best.rdb[bk] = best.rqd;
+    for (int bk = 0; bk < kOffBuckets; ++bk)
+        best.rob[bk] = best.rqo;
+    refine(best, best_t, true);
+    // the allocation is the largest group of any bucket
+    best.rqd = std::max({best.rdb[0], best.rdb[1], best.rdb[2]});
+    best.rqo = std::max(best.rob[0], best.rob[1]);
+
+    // 2. streaming frame: mapping x mode, then per bucket
     best_t = 1e30;
     const int caps[3] = {0, 256, 1024};
     for (int fused = 0; fused <= 1 && st == STA_OK; ++fused)
         for (auto& m : kMaps)
             for (int ci = 0; ci < (fused ? 3 : 1) && st == STA_OK; ++ci) {
-                sta_set_config(ctx, fused, best.rqd, best.rqo, m[0], m[1], caps[ci], best.nt);
-                std::vector<float> t;
-                for (int r = 0; r <= reps && st == STA_OK; ++r) {
-                    float ms = 0.0f;
-                    (void)hipEventRecord(a, s);
-                    st = sta_apply_edits(ctx, ids_dev, states_dev, n_edits, stream);
-                    (void)hipEventRecord(b, s);
-                    if (st == STA_OK)
-                        st = sta_apply_edits(ctx, ids_dev, inv_dev, n_edits, stream);
-                    (void)hipEventSynchronize(b);
-                    (void)hipEventElapsedTime(&ms, a, b);
-                    if (r > 0)
-                        t.push_back(ms);
-                }
-                const double med = median(t) * 1e3;
+                Cfg c = best;
+                c.fused = fused, c.sqd = m[0], c.sqo = m[1], c.cap = caps[ci];
+                for (int bk = 0; bk < kDiagBuckets; ++bk)
+                    c.sdb[bk] = m[0];
+                for (int bk = 0; bk < kOffBuckets; ++bk)
+                    c.sob[bk] = m[1];
+                const double med = time_frame(c);
                 std::snprintf(line, sizeof line, "frame    %s map %2dx%d cap %4d: %9.2f us\n",
                               fused ? "fused" : "2-launch", m[0], m[1], caps[ci], med);
                 rep += line;
@@ -274,16 +413,23 @@ sta_status sta_autotune(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* sta
                     best.cap = caps[ci];
                 }
             }
+    for (int bk = 0; bk < kDiagBuckets; ++bk)
+        best.sdb[bk] = best.sqd;
+    for (int bk = 0; bk < kOffBuckets; ++bk)
+        best.sob[bk] = best.sqo;
+    refine(best, best_t, false);
+    best.sqd = std::max({best.sdb[0], best.sdb[1], best.sdb[2]});
+    best.sqo = std::max(best.sob[0], best.sob[1]);
+
     ctx->timing = saved_timing;
     if (st == STA_OK && hipStreamSynchronize(s) == hipSuccess && sta_status_sync(ctx, stream) == STA_OK) {
-        sta_set_config(ctx, best.fused, best.rqd, best.rqo, best.sqd, best.sqo, best.cap, best.nt);
-        std::snprintf(line, sizeof line, "chosen: fused %d rebuild %dx%d nt %d stream %dx%d cap %d\n", best.fused,
-                      best.rqd, best.rqo, best.nt, best.sqd, best.sqo, best.cap);
+        st = apply(ctx, best);
+        std::snprintf(line, sizeof line, "chosen: %s\n", describe(best).c_str());
         rep += line;
-        if (cache)
+        if (cache && st == STA_OK)
             cache_store(cache, key, best);
     } else {
-        sta_set_config(ctx, saved.fused, saved.rqd, saved.rqo, saved.sqd, saved.sqo, saved.cap, saved.nt);
+        (void)apply(ctx, saved);
         if (st == STA_OK)
             st = STA_EHIP;
     }

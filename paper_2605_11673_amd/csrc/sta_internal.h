@@ -33,12 +33,45 @@ struct Ctl {
     int32_t pad;
 };
 
-// Slot mapping: lanes per block value for diagonal / off-diagonal blocks
-// (1 thread-, 4 quad-, 16 wave-sixteenth-per-slot; diagonal 1/4/16, off 1/4).
+// Incidence-length buckets of the slot mapping: a block's segment length
+// kappa (its number of candidate tets) puts a diagonal block in bucket 0
+// (kappa <= 8), 1 (9..32) or 2 (> 32), an off-diagonal block in bucket 0
+// (kappa <= 8) or 1 (> 8).
+constexpr int kDiagBuckets = 3, kOffBuckets = 2;
+__host__ __device__ inline int diag_bucket(int kappa)
+{
+    return kappa <= 8 ? 0 : (kappa <= 32 ? 1 : 2);
+}
+__host__ __device__ inline int off_bucket(int kappa)
+{
+    return kappa <= 8 ? 0 : 1;
+}
+
+// Slot mapping: lanes per block value (1 thread-, 4 quad-, 16
+// wave-sixteenth-per-slot; diagonal 1/4/16, off-diagonal 1/4), chosen per
+// incidence-length bucket (qdb, qob).  qd / qo are the lanes allocated per
+// value, the largest bucket mapping; a block whose bucket uses fewer leaves
+// the rest of its lanes idle.
 struct MapConfig {
     int qd = 1, qo = 1;
     int nt = 0;  // non-temporal cache hints (rebuild only)
+    int qdb[kDiagBuckets] = {1, 1, 1};
+    int qob[kOffBuckets] = {1, 1};
 };
+
+// One mapping for every bucket.
+inline MapConfig uniform_map(int qd, int qo, int nt)
+{
+    MapConfig m;
+    m.qd = qd;
+    m.qo = qo;
+    m.nt = nt;
+    for (int b = 0; b < kDiagBuckets; ++b)
+        m.qdb[b] = qd;
+    for (int b = 0; b < kOffBuckets; ++b)
+        m.qob[b] = qo;
+    return m;
+}
 
 // Material constants, evaluated once on the host in the fixed order.
 struct Material {
@@ -145,6 +178,7 @@ struct sta_ctx {
     std::vector<void*> owned;   // every device allocation
     // execution configuration (sta_set_config / sta_autotune)
     sta::MapConfig rebuild_map, stream_map;
+    int64_t bucket_blocks[sta::kDiagBuckets + sta::kOffBuckets] = {};  // blocks per incidence-length bucket
     int fused = 0;          // 1: one persistent launch per frame
     int frame_grid_cap = 0; // 0: occupancy limit only
     int frame_max_grid = 0; // co-resident workgroups for the fused kernel (per stream_map)

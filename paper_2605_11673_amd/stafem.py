@@ -63,6 +63,8 @@ SIGNATURES = {
     "sta_components": (_int, [_vp, _vp, _i64p, _vp]),
     "sta_set_config": (_int, [_vp, _int, _int, _int, _int, _int, _int, _int]),
     "sta_get_config": (_int, [_vp, ctypes.POINTER(_int)]),
+    "sta_set_bucket_map": (_int, [_vp, _int, _vp, _vp]),
+    "sta_get_bucket_map": (_int, [_vp, _int, _vp, _vp, _vp]),
     "sta_autotune": (_int, [_vp, _vp, _vp, _i64, _int, _vp, ctypes.c_char_p, _i64]),
     "sta_batch_build": (_int, [_int, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _dbl, _vp, _vp, ctypes.POINTER(_vp)]),
     "sta_batch_offsets": (_int, [_vp, ctypes.POINTER(_int), _vp, _vp, _vp, _vp, _i64]),
@@ -326,6 +328,20 @@ class Assembler:
         out = (ctypes.c_int * 7)()
         _check(load().sta_get_config(self._ctx, out), self._ctx)
         return dict(zip(self.CONFIG, list(out)))
+
+    def set_bucket_map(self, which: str, diag, off):
+        """Slot mapping per incidence-length bucket (see sta_set_bucket_map): which is
+        "rebuild" or "stream", diag three group sizes in {1, 4, 16} (kappa <= 8, 9..32,
+        > 32), off two in {1, 4} (kappa <= 8, > 8)."""
+        qd = (ctypes.c_int * 3)(*[int(x) for x in diag])
+        qo = (ctypes.c_int * 2)(*[int(x) for x in off])
+        _check(load().sta_set_bucket_map(self._ctx, {"rebuild": 0, "stream": 1}[which], qd, qo), self._ctx)
+
+    def bucket_map(self, which: str) -> dict:
+        """The mapping per bucket and the number of blocks in each bucket."""
+        qd, qo, nb = (ctypes.c_int * 3)(), (ctypes.c_int * 2)(), (ctypes.c_int64 * 5)()
+        _check(load().sta_get_bucket_map(self._ctx, {"rebuild": 0, "stream": 1}[which], qd, qo, nb), self._ctx)
+        return {"diag": list(qd), "off": list(qo), "diag_blocks": list(nb)[:3], "off_blocks": list(nb)[3:]}
 
     def autotune(self, ids: torch.Tensor, states: torch.Tensor, reps: int = 7, stream=None) -> str:
         """Pick slot mappings and frame mode by timing (see sta_autotune); returns the report."""
