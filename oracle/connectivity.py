@@ -3,12 +3,20 @@
 The paper tracks tetrahedron connectivity under the edit stream, rebuilt
 periodically from the active mask and spot-checked by sampled breadth-first
 searches (Sec. 3.6; Alg. 1 keeps it with the mask).  It does not say when two
-tetrahedra count as connected.  Reading used here: two active tets are
-connected when they share a vertex, i.e. the components are those of the
-assembled operator (tets that share a vertex share its degrees of freedom);
-this also joins the two sides of a hanging-node interface in the refinement
-superset.  A component is labelled by the smallest vertex id it contains, so
-labels do not depend on the order in which an algorithm discovers them.
+tetrahedra count as connected, so two adjacencies are provided:
+
+* vertex: two active tets are connected when they share a vertex, i.e. the
+  components are those of the assembled operator (tets that share a vertex
+  share its degrees of freedom); this also joins the two sides of a
+  hanging-node interface in the refinement superset.  A component is labelled
+  by the smallest vertex id it contains.
+* face: two active tets are connected when they share a face (the same three
+  vertices), the usual notion of a fragment in fracture: pieces that touch
+  only along an edge or at a vertex are apart.  A component is labelled by
+  the smallest tet id it contains.
+
+Labels do not depend on the order in which an algorithm discovers the
+components.
 """
 from collections import deque
 
@@ -60,4 +68,70 @@ def bfs_component(n_nodes: int, tets, mask, start: int, by_node=None):
                 if f not in seen:
                     seen.add(f)
                     q.append(f)
+    return seen
+
+
+def face_pairs(tets):
+    """All pairs (e, f), e < f, of candidate tets with a common face: the four
+    vertex triples of every tet, sorted, grouped by equal triples (a library sort)."""
+    t = np.sort(np.asarray(tets, dtype=np.int64), axis=1)
+    m = len(t)
+    tri = np.concatenate([np.delete(t, a, axis=1) for a in range(4)])  # 4m sorted triples
+    owner = np.tile(np.arange(m, dtype=np.int64), 4)
+    order = np.lexsort((owner, tri[:, 2], tri[:, 1], tri[:, 0]))
+    tri, owner = tri[order], owner[order]
+    if len(tri) == 0:
+        return np.zeros((0, 2), dtype=np.int64)
+    same = np.all(tri[1:] == tri[:-1], axis=1)
+    start = np.concatenate([[0], np.nonzero(~same)[0] + 1])
+    length = np.diff(np.concatenate([start, [len(tri)]]))
+    two = start[length == 2]
+    pairs = [np.stack([owner[two], owner[two + 1]], axis=1)]
+    for i, k in zip(start[length > 2], length[length > 2]):  # more than two tets on one triple
+        g = owner[i:i + k]
+        pairs.append(np.array([(g[u], g[v]) for u in range(k) for v in range(u + 1, k)], dtype=np.int64))
+    p = np.concatenate(pairs).reshape(-1, 2)
+    p = np.sort(p, axis=1)
+    return np.unique(p, axis=0)
+
+
+def face_components(tets, mask, pairs=None):
+    """Per-tet label (smallest tet id of its face-connected component; -1 for inactive
+    tets) and the number of components (library connected_components on the graph
+    whose edges are the face pairs with both tets active)."""
+    on = np.asarray(mask).astype(bool)
+    m = len(on)
+    if pairs is None:
+        pairs = face_pairs(tets)
+    p = pairs[on[pairs[:, 0]] & on[pairs[:, 1]]] if len(pairs) else pairs
+    g = sp.coo_matrix((np.ones(len(p)), (p[:, 0], p[:, 1])), shape=(m, m))
+    _, comp = connected_components(g, directed=False)
+    ids = np.nonzero(on)[0]
+    smallest = np.full(comp.max() + 1 if m else 0, np.iinfo(np.int64).max)
+    np.minimum.at(smallest, comp[ids], ids)
+    label = np.full(m, -1, dtype=np.int64)
+    label[on] = smallest[comp[ids]]
+    return label, int(len(np.unique(label[on])))
+
+
+def bfs_face_component(tets, mask, start: int, by_node=None):
+    """The set of active tets reachable from active tet `start` through shared faces:
+    breadth-first search where neighbours are found by comparing vertex sets directly
+    (three common vertices), without the sorted-triple grouping of face_pairs.
+    by_node: tets_by_node of the same mask, if already built."""
+    t = np.asarray(tets, dtype=np.int64)
+    if by_node is None:
+        by_node = tets_by_node(int(t.max()) + 1 if len(t) else 0, tets, mask)
+    seen = {int(start)}
+    q = deque([int(start)])
+    while q:
+        e = q.popleft()
+        ve = set(int(a) for a in t[e])
+        cand = set()
+        for a in ve:
+            cand.update(by_node[a])
+        for f in cand:
+            if f not in seen and len(ve & set(int(a) for a in t[f])) == 3:
+                seen.add(f)
+                q.append(f)
     return seen
