@@ -622,39 +622,47 @@ def euler_section(torch, stafem, workloads, w, frames, cfg, args, rtol=1e-8):
 
 
 def connectivity_section(torch, stafem, w, frames, args):
-    """Connectivity rebuilt from the mask after every frame of the headline stream
-    (union-find over the active tets' vertices): time per rebuild and the component
-    count along the stream; each rebuild is repeated and must give identical labels."""
+    """Connectivity rebuilt from the mask after every frame of the headline stream, for
+    both adjacencies (union-find over the active tets' vertices; over the candidate face
+    pairs): time per rebuild and the component count along the stream; each rebuild is
+    repeated and must give identical labels."""
     asm = stafem.Assembler.from_workload(w)
     dfr = [stafem.upload_frame(ids, st) for ids, st in frames]
     lab = torch.empty(w.n_tets, dtype=torch.int32, device="cuda")
     import ctypes
 
     lib = stafem.load()
+    fns = {"vertex": lib.sta_components, "face": lib.sta_face_components}
+    asm.components("face")  # the face pairs are found once per context, outside the timing
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    times, counts, stable = [], [], True
+    res = {a: {"times": [], "counts": [], "stable": True} for a in fns}
     for ids, st in dfr:
         asm.apply_edits(ids, st)
-        torch.cuda.synchronize()
-        torch.cuda._sleep(200000)
-        ev[0].record()
-        code = lib.sta_components(asm.handle, ctypes.c_void_p(lab.data_ptr()), None,
-                                  ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
-        ev[1].record()
-        ev[1].synchronize()
-        assert code == stafem.STA_OK
-        times.append(ev[0].elapsed_time(ev[1]) * 1e3)
-        again, k = asm.components()
-        stable = stable and bool(torch.equal(again, lab))
-        counts.append(k)
+        for adj, fn in fns.items():
+            torch.cuda.synchronize()
+            torch.cuda._sleep(200000)
+            ev[0].record()
+            code = fn(asm.handle, ctypes.c_void_p(lab.data_ptr()), None,
+                      ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+            ev[1].record()
+            ev[1].synchronize()
+            assert code == stafem.STA_OK
+            r = res[adj]
+            r["times"].append(ev[0].elapsed_time(ev[1]) * 1e3)
+            again, k = asm.components(adj)
+            r["stable"] = r["stable"] and bool(torch.equal(again, lab))
+            r["counts"].append(k)
     asm.close()
-    out = {"workload": "components of the active tets (shared-vertex adjacency) rebuilt after every frame of the "
-                       "headline stream",
-           "rebuild_us_median": round(float(np.median(times)), 3), "rebuild_us_max": round(float(np.max(times)), 3),
-           "components_initial": counts[0], "components_max": int(max(counts)), "components_final": counts[-1],
-           "repeat_labels_identical": stable}
-    log(f"[bench] connectivity: {out['rebuild_us_median']} us per rebuild, components {counts[0]} -> "
-        f"{max(counts)} -> {counts[-1]}")
+    out = {"workload": "components of the active tets rebuilt after every frame of the headline stream, "
+                       "shared-vertex and shared-face adjacency"}
+    for adj, r in res.items():
+        c = r["counts"]
+        out[adj] = {"rebuild_us_median": round(float(np.median(r["times"])), 3),
+                    "rebuild_us_max": round(float(np.max(r["times"])), 3),
+                    "components_initial": c[0], "components_max": int(max(c)), "components_final": c[-1],
+                    "repeat_labels_identical": r["stable"]}
+        log(f"[bench] connectivity ({adj}): {out[adj]['rebuild_us_median']} us per rebuild, components "
+            f"{c[0]} -> {max(c)} -> {c[-1]}")
     return out
 
 

@@ -246,6 +246,19 @@ sta_status sta_euler_step(sta_ctx* ctx, double* u_dev, double* v_dev, const doub
  * (the host checks convergence after each pass). */
 sta_status sta_components(sta_ctx* ctx, int32_t* labels_dev, int64_t* n_components, void* stream);
 
+/* Connectivity over shared faces (Sec. 3.6 leaves the adjacency open; this
+ * is the fragment notion of fracture): two active tets are connected when
+ * they have three vertices in common, so pieces touching only along an edge
+ * or at a vertex are apart, and a hanging-node interface of a refinement
+ * superset separates.  labels_dev (device, n_tets int32) receives, per tet,
+ * its component's smallest tet id, or -1 for an inactive tet;
+ * *n_components (may be NULL) the number of components.  The candidate
+ * pairs with a common face are found on the first call (a host sort of the
+ * 4 n_tets vertex triples) and kept on the device with the context (8 B per
+ * pair, 4 B per tet).  Synchronises `stream`.  Errors: STA_EINVAL,
+ * STA_ENOMEM, STA_EHIP. */
+sta_status sta_face_components(sta_ctx* ctx, int32_t* labels_dev, int64_t* n_components, void* stream);
+
 /* Execution configuration.
  *   fused       0: a frame is two launches (edit phase, touched phase);
  *               1: one persistent launch (both phases, grid barrier between).

@@ -116,22 +116,29 @@ def face_components(tets, mask, pairs=None):
 
 def bfs_face_component(tets, mask, start: int, by_node=None):
     """The set of active tets reachable from active tet `start` through shared faces:
-    breadth-first search where neighbours are found by comparing vertex sets directly
-    (three common vertices), without the sorted-triple grouping of face_pairs.
+    breadth-first search where the neighbours across each face of a tet are the tets
+    that hold all three of its vertices (intersections of the per-vertex tet lists),
+    without the sorted-triple grouping of face_pairs.
     by_node: tets_by_node of the same mask, if already built."""
     t = np.asarray(tets, dtype=np.int64)
     if by_node is None:
         by_node = tets_by_node(int(t.max()) + 1 if len(t) else 0, tets, mask)
+    sets = {}
+
+    def around(a):
+        if a not in sets:
+            sets[a] = set(by_node[a])
+        return sets[a]
+
     seen = {int(start)}
     q = deque([int(start)])
     while q:
         e = q.popleft()
-        ve = set(int(a) for a in t[e])
-        cand = set()
-        for a in ve:
-            cand.update(by_node[a])
-        for f in cand:
-            if f not in seen and len(ve & set(int(a) for a in t[f])) == 3:
-                seen.add(f)
-                q.append(f)
+        v = [int(a) for a in t[e]]
+        for skip in range(4):  # the tets holding all three vertices of each face of e
+            a, b, c = [v[i] for i in range(4) if i != skip]
+            for f in around(a) & around(b) & around(c):
+                if f not in seen:
+                    seen.add(f)
+                    q.append(f)
     return seen

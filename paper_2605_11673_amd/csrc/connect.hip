@@ -1,8 +1,14 @@
 // Connectivity of the active tetrahedra (paper Sec. 3.6: rebuilt from the
 // current mask; Alg. 1 keeps it with the mask), on gfx950.
 //
-// Two active tets are connected when they share a vertex (the components of
-// the assembled operator).  Components are found over the vertices by
+// The paper does not fix the adjacency; two are provided.  Vertex: two
+// active tets are connected when they share a vertex (the components of the
+// assembled operator), labelled by the component's smallest vertex.  Face:
+// when they share a face (fragments in the sense of fracture), labelled by
+// the component's smallest tet; the candidate pairs with a common vertex
+// triple are found once on the host and kept on the device.
+//
+// Vertex adjacency: components are found over the vertices by
 // hooking roots and shortcutting (a Shiloach-Vishkin style iteration): every
 // vertex keeps a parent pointer f, initially itself; in a hooking pass each
 // active tet climbs from its four vertices to their roots and lowers the
@@ -17,6 +23,10 @@
 // monotone atomic minimum); the launch boundary makes all updates visible to
 // the next pass.  The host checks a change flag after each hooking pass.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <vector>
 
 #include "sta_internal.h"
 
@@ -133,7 +143,155 @@ __global__ __launch_bounds__(kBlock) void k_cc_count(int n_nodes, const int* __r
         atomicAdd(flag + 1, s_count);
 }
 
+// Face adjacency: parent pointers over tets, each starting at itself.
+__global__ __launch_bounds__(kBlock) void k_ccf_init(int n_tets, int* f)
+{
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e < n_tets)
+        f[e] = e;
+}
+
+// Hooking pass over the face pairs whose two tets are both active.
+__global__ __launch_bounds__(kBlock) void k_ccf_hook(const uint8_t* __restrict__ mask, const int2* __restrict__ pairs,
+                                                     int64_t n_pairs, int* f, uint32_t* flag)
+{
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n_pairs)
+        return;
+    const int2 p = pairs[k];
+    if (!mask[p.x] || !mask[p.y])
+        return;
+    const int ra = climb(f, p.x), rb = climb(f, p.y);
+    if (ra == rb)
+        return;
+    const int lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
+    bool changed = atomicMin(f + hi, lo) > lo;
+    changed |= atomicMin(f + p.x, lo) > lo;
+    changed |= atomicMin(f + p.y, lo) > lo;
+    if (changed)
+        flag[0] = 1u;
+}
+
+// Label every tet with its root (-1 if inactive); count the active roots.
+__global__ __launch_bounds__(kBlock) void k_ccf_label(int n_tets, const uint8_t* __restrict__ mask,
+                                                      const int* __restrict__ f, int32_t* __restrict__ label,
+                                                      uint32_t* flag)
+{
+    __shared__ uint32_t s_count;
+    if (threadIdx.x == 0)
+        s_count = 0u;
+    __syncthreads();
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e < n_tets) {
+        const bool on = mask[e] != 0;
+        const int r = f[e];
+        label[e] = on ? r : -1;
+        if (on && r == e)
+            atomicAdd(&s_count, 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_count)
+        atomicAdd(flag + 1, s_count);
+}
+
 }  // namespace
+
+// Candidate tet pairs with a common face (sorted vertex triple), every pair
+// of tets on one triple, (smaller id, larger id), sorted.
+std::vector<int2> host_face_pairs(const std::vector<int4>& T)
+{
+    struct Face {
+        int a, b, c, e;
+    };
+    std::vector<Face> fs;
+    fs.reserve(4 * T.size());
+    for (size_t e = 0; e < T.size(); ++e) {
+        std::array<int, 4> v = {T[e].x, T[e].y, T[e].z, T[e].w};
+        std::sort(v.begin(), v.end());
+        for (int skip = 0; skip < 4; ++skip) {
+            int t[3], k = 0;
+            for (int i = 0; i < 4; ++i)
+                if (i != skip)
+                    t[k++] = v[i];
+            fs.push_back(Face{t[0], t[1], t[2], (int)e});
+        }
+    }
+    std::sort(fs.begin(), fs.end(), [](const Face& x, const Face& y) {
+        if (x.a != y.a) return x.a < y.a;
+        if (x.b != y.b) return x.b < y.b;
+        if (x.c != y.c) return x.c < y.c;
+        return x.e < y.e;
+    });
+    std::vector<int2> pairs;
+    for (size_t i = 0; i < fs.size();) {
+        size_t j = i + 1;
+        while (j < fs.size() && fs[j].a == fs[i].a && fs[j].b == fs[i].b && fs[j].c == fs[i].c)
+            ++j;
+        for (size_t u = i; u < j; ++u)
+            for (size_t w = u + 1; w < j; ++w)
+                if (fs[u].e != fs[w].e)
+                    pairs.push_back(make_int2(fs[u].e, fs[w].e));
+        i = j;
+    }
+    std::sort(pairs.begin(), pairs.end(),
+              [](const int2& x, const int2& y) { return x.x != y.x ? x.x < y.x : x.y < y.y; });
+    pairs.erase(std::unique(pairs.begin(), pairs.end(), [](const int2& x, const int2& y) { return x.x == y.x && x.y == y.y; }),
+                pairs.end());
+    return pairs;
+}
+
+// Face-adjacency labels (smallest tet id of the component, -1 if inactive)
+// into label; *n_components on the host.  f: n_tets ints; synchronises s.
+hipError_t run_face_components(const DevView& v, const int2* pairs, int64_t n_pairs, int* f, uint32_t* flag,
+                               uint32_t* host_flag, int32_t* label, int64_t* n_components, int* passes,
+                               hipStream_t s)
+{
+    const unsigned gt = v.n_tets > 0 ? blocks(v.n_tets) : 1u;
+    hipError_t e = hipSuccess;
+    *passes = 0;
+    if (v.n_tets > 0) {
+        hipLaunchKernelGGL(k_ccf_init, dim3(gt), dim3(kBlock), 0, s, v.n_tets, f);
+        e = hipGetLastError();
+    }
+    for (int phase = 0; phase < 2 && e == hipSuccess; ++phase) {
+        for (int it = 0;; ++it) {
+            if (it > v.n_tets + 2)
+                return hipErrorUnknown;
+            e = hipMemsetAsync(flag, 0, sizeof(uint32_t), s);
+            if (e == hipSuccess && phase == 0 && n_pairs > 0) {
+                hipLaunchKernelGGL(k_ccf_hook, dim3((unsigned)((n_pairs + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                                   v.mask, pairs, n_pairs, f, flag);
+                e = hipGetLastError();
+            }
+            if (e == hipSuccess && v.n_tets > 0) {
+                hipLaunchKernelGGL(k_cc_shortcut, dim3(gt), dim3(kBlock), 0, s, v.n_tets, f, flag + (phase == 0));
+                e = hipGetLastError();
+            }
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(host_flag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(s);
+            if (e != hipSuccess)
+                return e;
+            ++*passes;
+            if (*host_flag == 0u)
+                break;
+        }
+    }
+    if (e == hipSuccess)
+        e = hipMemsetAsync(flag + 1, 0, sizeof(uint32_t), s);
+    if (e == hipSuccess && v.n_tets > 0) {
+        hipLaunchKernelGGL(k_ccf_label, dim3(gt), dim3(kBlock), 0, s, v.n_tets, v.mask, f, label, flag);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host_flag, flag + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e == hipSuccess)
+        *n_components = *host_flag;
+    return e;
+}
 
 // Component labels into label (device, n_tets); *n_components on the host.
 // Synchronises s.  Returns hipErrorUnknown if the iteration bound is hit.
@@ -212,6 +370,8 @@ extern "C" sta_status sta_components(sta_ctx* ctx, int32_t* labels_dev, int64_t*
         }
         ctx->owned.push_back(q);
         ctx->cc_ws = static_cast<int32_t*>(q);
+    }
+    if (!ctx->cc_host) {
         e = hipHostMalloc((void**)&ctx->cc_host, sizeof(uint32_t), hipHostMallocDefault);
         if (e != hipSuccess) {
             ctx->cc_host = nullptr;
@@ -230,6 +390,68 @@ extern "C" sta_status sta_components(sta_ctx* ctx, int32_t* labels_dev, int64_t*
     }
     if (e != hipSuccess) {
         ctx->errmsg = std::string("connectivity: ") + hipGetErrorString(e);
+        return STA_EHIP;
+    }
+    if (n_components)
+        *n_components = k;
+    return STA_OK;
+}
+
+extern "C" sta_status sta_face_components(sta_ctx* ctx, int32_t* labels_dev, int64_t* n_components, void* stream)
+{
+    if (!ctx || (ctx->n_tets > 0 && !labels_dev))
+        return STA_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (!ctx->ccf_ws) {
+        // the candidate face pairs, once per context (the candidate pool is fixed)
+        std::vector<int4> T((size_t)ctx->n_tets);
+        if (ctx->n_tets > 0)
+            e = hipMemcpy(T.data(), ctx->v.T, sizeof(int4) * T.size(), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            ctx->errmsg = std::string("face connectivity: ") + hipGetErrorString(e);
+            return STA_EHIP;
+        }
+        const std::vector<int2> pairs = host_face_pairs(T);
+        void* q = nullptr;
+        const size_t bytes = sizeof(int32_t) * ((size_t)ctx->n_tets + 2) + sizeof(int2) * (pairs.size() + 1);
+        e = hipMalloc(&q, bytes);
+        if (e != hipSuccess) {
+            ctx->errmsg = std::string("face connectivity workspace: ") + hipGetErrorString(e);
+            return STA_ENOMEM;
+        }
+        ctx->owned.push_back(q);
+        int32_t* base = static_cast<int32_t*>(q);
+        int2* pd = reinterpret_cast<int2*>(base + ((ctx->n_tets + 2 + 1) / 2) * 2);  // 8-byte aligned after f and flags
+        if (!pairs.empty())
+            e = hipMemcpy(pd, pairs.data(), sizeof(int2) * pairs.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            ctx->errmsg = std::string("face pairs upload: ") + hipGetErrorString(e);
+            return STA_EHIP;
+        }
+        ctx->ccf_ws = base;
+        ctx->ccf_pairs = pd;
+        ctx->ccf_npairs = (int64_t)pairs.size();
+    }
+    if (!ctx->cc_host) {
+        e = hipHostMalloc((void**)&ctx->cc_host, sizeof(uint32_t), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            ctx->cc_host = nullptr;
+            ctx->errmsg = std::string("connectivity host flag: ") + hipGetErrorString(e);
+            return STA_ENOMEM;
+        }
+    }
+    int* f = ctx->ccf_ws;
+    uint32_t* flag = reinterpret_cast<uint32_t*>(ctx->ccf_ws + ctx->n_tets);
+    int64_t k = 0;
+    e = run_face_components(ctx->v, ctx->ccf_pairs, ctx->ccf_npairs, f, flag, ctx->cc_host, labels_dev, &k,
+                            &ctx->cc_passes, s);
+    if (e == hipErrorUnknown) {
+        ctx->errmsg = "face connectivity: pass bound exceeded (labels invalid)";
+        return STA_EHIP;
+    }
+    if (e != hipSuccess) {
+        ctx->errmsg = std::string("face connectivity: ") + hipGetErrorString(e);
         return STA_EHIP;
     }
     if (n_components)

@@ -194,7 +194,10 @@ struct sta_ctx {
     double* euler_ws = nullptr;     // implicit Euler: M_t, right-hand side, new u (3 x n_rows)
     int32_t* cc_ws = nullptr;       // connectivity: parent and mark per node, 2 flags
     uint32_t* cc_host = nullptr;    // pinned flag read back after each pass
-    int cc_passes = 0;              // passes of the last sta_components
+    int cc_passes = 0;              // passes of the last sta_components / sta_face_components
+    int32_t* ccf_ws = nullptr;      // face connectivity: parent per tet, 2 flags, then the face pairs
+    int2* ccf_pairs = nullptr;      // candidate tet pairs with a common face
+    int64_t ccf_npairs = 0;
     // batch layout: per mesh node / tet / value offsets (k+1 entries)
     std::vector<int64_t> node_off, tet_off, nnz_off;
     std::string errmsg;

@@ -61,6 +61,7 @@ SIGNATURES = {
     "sta_lumped_mass": (_int, [_vp, _vp, _vp]),
     "sta_euler_step": (_int, [_vp, _vp, _vp, _vp, _dbl, _int, _vp, ctypes.POINTER(_int), ctypes.POINTER(_dbl)]),
     "sta_components": (_int, [_vp, _vp, _i64p, _vp]),
+    "sta_face_components": (_int, [_vp, _vp, _i64p, _vp]),
     "sta_set_config": (_int, [_vp, _int, _int, _int, _int, _int, _int, _int]),
     "sta_get_config": (_int, [_vp, ctypes.POINTER(_int)]),
     "sta_set_bucket_map": (_int, [_vp, _int, _vp, _vp]),
@@ -313,11 +314,14 @@ class Assembler:
                                      _stream_handle(stream), ctypes.byref(it), ctypes.byref(rr)), self._ctx)
         return it.value, rr.value
 
-    def components(self, stream=None):
-        """(labels int32 CUDA tensor (n_tets,), number of components); synchronises."""
+    def components(self, adjacency: str = "vertex", stream=None):
+        """(labels int32 CUDA tensor (n_tets,), number of components); synchronises.
+        adjacency "vertex" (sta_components: labels are smallest vertex ids) or "face"
+        (sta_face_components: labels are smallest tet ids)."""
+        fn = {"vertex": load().sta_components, "face": load().sta_face_components}[adjacency]
         lab = torch.empty(max(self.n_tets, 1), dtype=torch.int32, device="cuda")
         k = _i64()
-        _check(load().sta_components(self._ctx, _dev_ptr(lab), ctypes.byref(k), _stream_handle(stream)), self._ctx)
+        _check(fn(self._ctx, _dev_ptr(lab), ctypes.byref(k), _stream_handle(stream)), self._ctx)
         return lab[: self.n_tets], k.value
 
     def set_config(self, fused=0, rebuild_qd=1, rebuild_qo=1, stream_qd=1, stream_qo=1, grid_cap=0, rebuild_nt=0):

@@ -102,3 +102,110 @@ def test_refinement_and_batch():
     for j in range(6):
         assert np.all(lab[off["tet"][j]:off["tet"][j + 1]] == off["node"][j])
     b.close()
+
+
+# Face adjacency (sta_face_components): labels are the smallest tet id of the component.
+
+def check_face(asm, w, mask, pairs, what):
+    lab, k = gpu_face(asm)
+    ref, rk = C.face_components(w.tets, mask, pairs)
+    assert np.array_equal(lab, ref), f"{what}: {np.sum(lab != ref)} face labels differ"
+    assert k == rk, f"{what}: {k} vs {rk} face components"
+    return lab, k
+
+
+def gpu_face(asm):
+    lab, k = asm.components("face")
+    torch.cuda.synchronize()
+    return lab.cpu().numpy().astype(np.int64), k
+
+
+def test_face_fracture_stream_every_frame():
+    Sm = S()
+    w = W.make_fracture(seed=4, n=12, counts=[100, 400, 900, 300, 60])
+    frames = list(w.frames) + W.merge_stream(w.frames)
+    pairs = C.face_pairs(w.tets)
+    asm = Sm.Assembler.from_workload(w)
+    mask = w.mask0.copy()
+    ks = [check_face(asm, w, mask, pairs, "initial")[1]]
+    for t, (ids, st) in enumerate(frames):
+        asm.apply_edits(*Sm.upload_frame(ids, st))
+        mask[ids] = st
+        ks.append(check_face(asm, w, mask, pairs, f"frame {t}")[1])
+        if t % 3 == 0:  # the vertex labels on the same context stay right in between
+            check(asm, w, mask, f"vertex frame {t}")
+    assert ks[0] == 1 and max(ks) > 1 and ks[-1] == 1
+    asm.close()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_face_random_small_meshes(seed):
+    Sm = S()
+    w = W.random_small_mesh(seed, max_tets=40)
+    g = np.random.default_rng(seed)
+    asm = Sm.Assembler.from_workload(w)
+    pairs = C.face_pairs(w.tets)
+    check_face(asm, w, w.mask0, pairs, f"small{seed}")
+    every = np.arange(w.n_tets, dtype=np.int32)
+    for r in range(3):
+        mask = (g.uniform(size=w.n_tets) < 0.6).astype(np.uint8)
+        asm.apply_edits(*Sm.upload_frame(every, mask))
+        check_face(asm, w, mask, pairs, f"small{seed} mask {r}")
+        check(asm, w, mask, f"small{seed} mask {r} (vertex)")
+    asm.close()
+
+
+def test_face_full_size_with_bfs_spot_checks():
+    """40^3 fracture stream, face adjacency: labels vs the oracle at frames 0, 12, 23, 47;
+    at the peak frame, breadth-first searches (neighbours by direct vertex-set comparison)
+    from 20 sampled active tets reach exactly the tets with their GPU label."""
+    Sm = S()
+    w = W.make_fracture(seed=0)
+    frames = list(w.frames) + W.merge_stream(w.frames)
+    pairs = C.face_pairs(w.tets)
+    asm = Sm.Assembler.from_workload(w)
+    mask = w.mask0.copy()
+    for t, (ids, st) in enumerate(frames):
+        asm.apply_edits(*Sm.upload_frame(ids, st))
+        mask[ids] = st
+        if t in (0, 12, 23, 47):
+            lab, k = check_face(asm, w, mask, pairs, f"frame {t}")
+            print(f"[connect] face frame {t}: {k} components", flush=True)
+        if t == 12:
+            by = C.tets_by_node(w.n_nodes, w.tets, mask)
+            g = np.random.default_rng(1)
+            found = []  # components already searched: a sample inside one needs no new search
+            for e in g.choice(np.nonzero(mask)[0], size=20, replace=False):
+                comp = next((c for c in found if int(e) in c), None)
+                if comp is None:
+                    comp = C.bfs_face_component(w.tets, mask, int(e), by)
+                    found.append(comp)
+                assert comp == set(np.nonzero(lab == lab[e])[0].tolist())
+    asm.close()
+
+
+def test_face_refinement_and_batch():
+    """Refinement superset: hanging-node interfaces separate refined regions (many more
+    face components than vertex components); a batch of disjoint cubes: one component per
+    mesh, labelled by its first tet."""
+    Sm = S()
+    r = W.make_refinement(seed=3, n=8, frames=12)
+    pairs = C.face_pairs(r.tets)
+    asm = Sm.Assembler.from_workload(r)
+    mask = r.mask0.copy()
+    for t, (ids, st) in enumerate(r.frames):
+        asm.apply_edits(*Sm.upload_frame(ids, st))
+        mask[ids] = st
+        if t % 6 == 5:
+            _, kf = check_face(asm, r, mask, pairs, f"refinement frame {t}")
+            _, kv = check(asm, r, mask, f"refinement frame {t}")
+            assert kf >= kv
+    asm.close()
+    ws = W.make_batch(seed=3, count=6, sizes=[2, 4, 3, 1, 5, 2])
+    b = Sm.Batch.from_workloads(ws)
+    lab, k = gpu_face(b)
+    assert k == 6
+    off = b.offsets()
+    for j in range(6):
+        assert np.all(lab[off["tet"][j]:off["tet"][j + 1]] == off["tet"][j])
+    b.close()
