@@ -109,6 +109,19 @@ def load_traffic(kernel):
     return rec
 
 
+def load_frame_traffic():
+    """Per-frame HBM bytes of the two streaming kernels from the committed counter runs
+    (first pass over the headline step), or None if the kernel source changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha") != source_sha():
+        return None
+    return d.get("frames")
+
+
 def roofline(kernel, alg_bytes, seconds, launches, traffic_key=None, with_traffic=True):
     """with_traffic: attach the committed counter traffic (taken on the headline workload only)."""
     achieved = alg_bytes / seconds / 1e9 if seconds > 0 else 0.0
@@ -274,6 +287,7 @@ class Stream:
             return ev[0].elapsed_time(ev[1]) * 1e3
 
         rows, t_stream, t_cold, t_reb, t_reb_cold = [], [], [], [], []
+        ftr = load_frame_traffic() if self.headline else None
         for k, ((di, ds), st) in enumerate(zip(self.dframes, self.stats)):
             ids_h = self.frames_host[k][0]
             prev = torch.from_numpy(self.mask_before(k)[ids_h].copy()).cuda()  # undoes the frame
@@ -293,6 +307,11 @@ class Stream:
                          "rebuild_us": round(float(np.median(reb)), 3),
                          "rebuild_cold_us": round(float(np.median(reb_cold)), 3), "alg_bytes": alg,
                          "stream_gbs": round(alg / (np.median(warm) * 1e-6) / 1e9, 2)})
+            if ftr and k < len(ftr):
+                cb = ftr[k]["k_edits"] + ftr[k]["k_touched"]
+                rows[-1]["counter_bytes"] = cb
+                rows[-1]["counter_gbs"] = round(cb / (np.median(warm) * 1e-6) / 1e9, 2)
+                rows[-1]["counter_frac_of_peak"] = round(cb / (np.median(warm) * 1e-6) / 1e9 / HBM_PEAK_GBS, 5)
             t_stream.append(float(np.median(warm)))
             if cold:
                 t_cold.append(float(np.median(cold)))
