@@ -205,6 +205,10 @@ def test_empty_mesh_and_run_twice_determinism():
                       np.zeros(0, np.uint8))
     assert asm.nnz == 0 and asm.n_rows == 9
     asm.full_rebuild()
+    for adj in ("vertex", "face"):
+        lab, k = asm.components(adj)
+        assert k == 0 and lab.numel() == 0
+    assert asm.status_sync() == S.STA_OK
     asm.close()
     w = W.make_fracture(seed=4, n=8, counts=[60, 200, 90])
     runs = []
