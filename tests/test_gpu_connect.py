@@ -209,3 +209,21 @@ def test_face_refinement_and_batch():
     for j in range(6):
         assert np.all(lab[off["tet"][j]:off["tet"][j + 1]] == off["tet"][j])
     b.close()
+
+
+def test_all_inactive_and_all_active():
+    """Every tet deleted in one frame: no components, every label -1; every tet back: one."""
+    Sm = S()
+    w = W.make_fracture(seed=6, n=10, counts=[10])
+    pairs = C.face_pairs(w.tets)
+    asm = Sm.Assembler.from_workload(w)
+    every = np.arange(w.n_tets, dtype=np.int32)
+    asm.apply_edits(*Sm.upload_frame(every, np.zeros(w.n_tets, np.uint8)))
+    for adj in ("vertex", "face"):
+        lab, k = asm.components(adj)
+        assert k == 0 and bool((lab == -1).all())
+    asm.apply_edits(*Sm.upload_frame(every, np.ones(w.n_tets, np.uint8)))
+    check(asm, w, np.ones(w.n_tets, np.uint8), "all active (vertex)")
+    lab, k = check_face(asm, w, np.ones(w.n_tets, np.uint8), pairs, "all active (face)")
+    assert k == 1 and np.all(lab == 0)
+    asm.close()
