@@ -690,7 +690,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--reps", type=int, default=15, help="repetitions per frame for the per-frame breakdown")
+    ap.add_argument("--reps", type=int, default=40,
+                    help="repetitions per frame for the per-frame breakdown (half warm, half after a cache flush)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the refinement and batch workloads")
