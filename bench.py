@@ -698,7 +698,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default configuration")
     ap.add_argument("--config", default=None,
                     help="force fused,rebuild_qd,rebuild_qo,stream_qd,stream_qo,grid_cap,rebuild_nt (skips tuning)")
-    ap.add_argument("--cpu-sample", type=int, default=12, help="oracle rebuilds in the CPU baseline sample")
+    ap.add_argument("--cpu-sample", type=int, default=48, help="oracle rebuilds in the CPU baseline sample")
     ap.add_argument("--quick", action="store_true",
                     help="headline timed steps, 3 rebuilds and a 256 MiB reference copy only (for profiler runs)")
     args = ap.parse_args()
