@@ -104,6 +104,28 @@ def test_fracture_full_size_every_frame():
     asm.close()
 
 
+def test_fracture_full_size_tuned_configuration():
+    """The configuration the benchmark times: the autotuner's choice on the peak frame
+    (as bench.py makes it), then the 48-frame fracture+merge stream, every frame bitwise
+    equal to the oracle, and the rebuild under the tuned rebuild mapping at the end."""
+    S = stafem()
+    w = W.make_fracture(0)
+    frames = list(w.frames) + W.merge_stream(w.frames)
+    pat = oracle.pattern(w.n_nodes, w.tets)
+    asm = S.Assembler.from_workload(w)
+    rep = asm.autotune(*S.upload_frame(*frames[12]), reps=3)
+    print("[parity] tuned: " + rep.splitlines()[-1], flush=True)
+    mask = w.mask0.copy()
+    for t, (ids, st) in enumerate(frames):
+        mask[ids] = st
+        asm.apply_edits(*S.upload_frame(ids, st))
+        assert_bitwise(gpu_values(asm), oracle.rebuild_workload(w, mask, pat), f"tuned frame {t}")
+    asm.full_rebuild()
+    assert_bitwise(gpu_values(asm), oracle.rebuild_workload(w, mask, pat), "tuned rebuild")
+    assert asm.status_sync() == S.STA_OK
+    asm.close()
+
+
 def test_refinement_full_size():
     """432,000-tet red-refinement superset: 24 refine frames (1 parent off, 8 children on,
     children's contributions computed at build) then 24 merge frames, every frame bitwise."""
