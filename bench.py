@@ -640,6 +640,90 @@ def euler_section(torch, stafem, workloads, w, frames, cfg, args, rtol=1e-8):
     return out
 
 
+def bytes_cg_iteration(n_rows, nnz):
+    """One Jacobi-PCG iteration: the values once, one column index per 3x3 block, the row
+    pointers, and 13 vector passes (product: z, previous p, new p, q, 1/diag; update: x read
+    and written, new p, r read and written, q, 1/diag, z)."""
+    return 8 * nnz + 4 * (nnz // 9) + 4 * (n_rows + 1) + 13 * 8 * n_rows
+
+
+def bytes_adjoint(n_tets, n_active, n_nodes, n_blocks, nnz):
+    """Adjoint kernels: per tet its mask, 10 positions, 10 block ids, vertex ids, E, the
+    dL/dlogE and 4 vertex cotangent writes; the node coordinates; every block descriptor and
+    slot cotangent once; then per node its descriptor and its diagonal segment of vertex
+    cotangents (4 per tet), and dL/dx."""
+    per_tet = 1 + 40 + 40 + 16 + 8 + 8 + 96
+    return (n_tets * per_tet + 24 * n_nodes + 32 * n_blocks + 8 * nnz
+            + 4 * n_tets * 24 + n_nodes * (4 + 32 + 24))
+
+
+def gradient_section(torch, stafem, workloads, args, rtol=1e-10, reps=5):
+    """The differentiation workload: the fracture state after frame 12, compliance
+    L = f.u with A u = f.  Jacobi-PCG (time per iteration, bytes per iteration) and the
+    adjoint kernels (dL/dlogE, dL/dx from the slot cotangents -u u^T), each against the
+    HBM roofline; the GPU gradient against the oracle's complex-step adjoint for the same
+    cotangents; the oracle's PCG and adjoint timed on the host."""
+    import oracle
+
+    w, mask, f, _, _ = workloads.make_gradient_case(args.seed)
+    asm = stafem.Assembler(w.x, w.tets, w.E, w.nu, w.rho, w.dt, mask)
+    fd = torch.from_numpy(f.reshape(-1)).cuda()
+    u, it, rr = asm.cg_solve(fd, rtol=rtol)  # warm-up
+    asm.enable_kernel_timing(True)
+    asm.kernel_times()
+    iters = 0
+    for _ in range(reps):
+        u, it, rr = asm.cg_solve(fd, rtol=rtol)
+        iters += it
+    ks = asm.kernel_times()
+    gA = asm.slot_outer(u, u, -1.0)
+    gl, gx = asm.adjoint(gA)  # warm-up
+    asm.kernel_times()
+    for _ in range(reps):
+        gl, gx = asm.adjoint(gA)
+    ka = asm.kernel_times()
+    asm.enable_kernel_timing(False)
+    torch.cuda.synchronize()
+    n_solve, ms_solve = ks.get("solve", (0, 0.0))
+    n_adj, ms_adj = ka.get("adjoint", (0, 0.0))
+    it_us = ms_solve * 1e3 / max(iters, 1)
+    cg_bytes = bytes_cg_iteration(asm.n_rows, asm.nnz)
+    adj_bytes = bytes_adjoint(w.n_tets, int(mask.sum()), w.n_nodes, asm.n_diag_blocks + asm.n_off_blocks, asm.nnz)
+    out = {"workload": "fracture 40^3 after frames 0..12, compliance f.u with A u = f (gravity + surface load)",
+           "active_tets": int(mask.sum()),
+           "cg": {"rtol": rtol, "iterations": it, "relres": rr, "us_per_iteration": round(it_us, 3),
+                  "roofline": roofline("cg_iteration", cg_bytes * iters, ms_solve * 1e-3, iters,
+                                       with_traffic=False)},
+           "adjoint": {"us": round(ms_adj * 1e3 / max(n_adj, 1), 3),
+                       "roofline": roofline("k_adjoint_element+k_adjoint_nodes", adj_bytes * n_adj,
+                                            ms_adj * 1e-3, n_adj, with_traffic=False)}}
+    # the same cotangents through the oracle's complex-step adjoint, and the oracle timed
+    uh = u.cpu().numpy()
+    pat = oracle.pattern(w.n_nodes, w.tets)
+    r = np.repeat(np.arange(asm.n_rows), np.diff(pat[0]))
+    g_host = -(uh[r] * uh[pat[1]])
+    t0 = time.perf_counter()
+    ol, ox = oracle.adjoint(w.x, w.tets, w.E, w.nu, w.rho, w.dt, mask, pat[0], pat[1], g_host)
+    t_adj = time.perf_counter() - t0
+    gl_h, gx_h = gl.cpu().numpy(), gx.cpu().numpy()
+    rel = lambda a, b: float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+    out["adjoint"]["rel_err_vs_oracle"] = {"dlogE": rel(gl_h, ol), "dx": rel(gx_h, ox)}
+    vals = asm.values().cpu().numpy()
+    t0 = time.perf_counter()
+    _, oit, _ = oracle.pcg(pat[0], pat[1], vals, f.reshape(-1), rtol=rtol)
+    t_pcg = time.perf_counter() - t0
+    out["cpu_baseline"] = {"adjoint_s": round(t_adj, 3), "pcg_s_per_iteration": round(t_pcg / max(oit, 1), 5),
+                           "pcg_iterations": int(oit), "cores": 1, "kind": "oracle",
+                           "sample": "one oracle adjoint (complex step, C) and one oracle PCG solve (C) on the "
+                                     "same state, single-threaded"}
+    asm.close()
+    log(f"[bench] gradient: CG {it} it, {it_us:.2f} us/it ({out['cg']['roofline']['frac'] * 100:.1f}% of HBM peak); "
+        f"adjoint {out['adjoint']['us']} us ({out['adjoint']['roofline']['frac'] * 100:.1f}%), rel err vs oracle "
+        f"{max(out['adjoint']['rel_err_vs_oracle'].values()):.2e}; oracle adjoint {t_adj:.2f} s, "
+        f"PCG {t_pcg / max(oit, 1) * 1e3:.2f} ms/it")
+    return out
+
+
 def connectivity_section(torch, stafem, w, frames, args):
     """Connectivity rebuilt from the mask after every frame of the headline stream, for
     both adjacencies (union-find over the active tets' vertices; over the candidate face
@@ -778,6 +862,7 @@ def main():
         out["proxy"] = proxy_section(torch, stafem, w, frames, args)
         out["euler"] = euler_section(torch, stafem, workloads, w, frames, out["tuned_config"], args)
         out["connectivity"] = connectivity_section(torch, stafem, w, frames, args)
+        out["gradient"] = gradient_section(torch, stafem, workloads, args)
         r = workloads.make_refinement(args.seed)
         rf = r.frames[:24]
         rframes = rf + [(ids, (1 - st).astype(np.uint8)) for ids, st in reversed(rf)]
