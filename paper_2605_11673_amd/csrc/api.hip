@@ -807,6 +807,8 @@ sta_status sta_cg_solve(sta_ctx* ctx, const double* values_dev, const double* b_
     CgView c;
     c.n = n;
     c.nparts = (n + 255) / 256;
+    c.nparts_s = spmv_grid(n);
+    c.nparts_u = update_grid(n);
     c.rowptr = ctx->rowptr;
     c.colidx = ctx->colidx;
     c.vals = values_dev ? values_dev : ctx->v.values;
@@ -820,19 +822,20 @@ sta_status sta_cg_solve(sta_ctx* ctx, const double* values_dev, const double* b_
     c.part = c.dinv + n;
     c.s = ctx->cg_s;
     e = launch_cg_init(c, b_dev, rtol, s);
+    // iterations k = 0 .. max_iter (the last one only records the residual),
+    // 16 at a time between host checks
     const int chunk = 16;
-    int done_iters = 0;
+    int next = 0;
     while (e == hipSuccess) {
-        const int count = max_iter - done_iters < chunk ? max_iter - done_iters : chunk;
+        const int count = max_iter + 1 - next < chunk ? max_iter + 1 - next : chunk;
         if (count > 0)
-            e = timed(ctx, STA_KERNEL_SOLVE, s,
-                      [&] { return launch_cg_iterations(c, done_iters, count, max_iter, s); });
-        done_iters += count;
+            e = timed(ctx, STA_KERNEL_SOLVE, s, [&] { return launch_cg_iterations(c, next, count, max_iter, s); });
+        next += count;
         if (e == hipSuccess)
             e = hipMemcpyAsync(ctx->cg_host, ctx->cg_s, sizeof(CgScalars), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess)
             e = hipStreamSynchronize(s);
-        if (e != hipSuccess || ctx->cg_host->done || done_iters >= max_iter)
+        if (e != hipSuccess || ctx->cg_host->done || next > max_iter)
             break;
     }
     if (e == hipSuccess)

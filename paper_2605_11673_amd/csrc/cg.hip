@@ -5,17 +5,20 @@
 //
 // All scalars stay on the device; each kernel returns at once when the
 // solve has converged, so the host only synchronises every few iterations.
-// Dot products use a fixed reduction tree (per-workgroup tree, then one
-// workgroup over the partials in index order): results are reproducible
+// Dot products use fixed reduction trees (a per-workgroup tree, then a sum
+// over the workgroups' partials in index order): results are reproducible
 // run to run.
 //
-// One iteration is four launches: the matrix-vector product (which also
-// forms the new search direction p = z + beta p on the fly, from a second
-// copy of p, so no separate direction pass is needed), alpha, the x / r / z
-// update, beta.  The product works per node: the three rows of a node share
-// one column list (3x3 blocks), so a group of lanes walks the node's
-// neighbours once, reading one column index and one 3-vector of p per
-// neighbour for all three rows.
+// One iteration is two launches.  The matrix-vector product first sums the
+// previous update's partials of r.z and r.r (every workgroup the same way,
+// so all get the same bits), checks convergence, forms beta, and builds the
+// new search direction p = z + beta p on the fly from a second copy of p.
+// The update then sums the product's partials of p.Ap into alpha and
+// updates x, r, z with partials of r.z and r.r.  The product works per node:
+// the three rows of a node share one column list (3x3 blocks), so a group of
+// lanes walks the node's neighbours once, reading one column index and one
+// 3-vector of p per neighbour for all three rows.  Both grids are capped, so
+// that the partials every workgroup sums stay few.
 #include <hip/hip_runtime.h>
 
 #include "sta_internal.h"
@@ -26,6 +29,14 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kNodeLanes = 16;  // lanes per node (three CSR rows) in the matrix-vector product
+#ifndef STA_CG_SPMV_GRID
+#define STA_CG_SPMV_GRID 2048
+#endif
+#ifndef STA_CG_UPDATE_GRID
+#define STA_CG_UPDATE_GRID 256
+#endif
+constexpr int kSpmvGridMax = STA_CG_SPMV_GRID;
+constexpr int kUpdateGridMax = STA_CG_UPDATE_GRID;
 
 // Workgroup sum of one value per thread, fixed tree; result valid in thread 0.
 __device__ __forceinline__ double block_sum(double x, double* sh)
@@ -59,6 +70,50 @@ __device__ __forceinline__ double reduce_partials(const double* __restrict__ p, 
     for (; i < n; i += kBlock)
         acc = acc + p[i];
     return block_sum(acc, sh);
+}
+
+// Workgroup sums of two values per thread, fixed trees; results valid in every thread.
+__device__ __forceinline__ void block_sum2(double x, double y, double* sh, double& sx, double& sy)
+{
+    sh[threadIdx.x] = x;
+    sh[kBlock + threadIdx.x] = y;
+    __syncthreads();
+#pragma unroll
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + s];
+            sh[kBlock + threadIdx.x] = sh[kBlock + threadIdx.x] + sh[kBlock + threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    sx = sh[0];
+    sy = sh[kBlock];
+}
+
+// Sums of p[0..n) and q[0..n) in one pass, each in the order of reduce_partials.
+__device__ __forceinline__ void reduce_partials2(const double* __restrict__ p, const double* __restrict__ q, int n,
+                                                 double* sh, double& sp, double& sq)
+{
+    double a = 0.0, b = 0.0;
+    int i = threadIdx.x;
+    for (; i + 7 * kBlock < n; i += 8 * kBlock) {
+        double t[8], u[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            t[k] = p[i + k * kBlock];
+            u[k] = q[i + k * kBlock];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            a = a + t[k];
+            b = b + u[k];
+        }
+    }
+    for (; i < n; i += kBlock) {
+        a = a + p[i];
+        b = b + q[i];
+    }
+    block_sum2(a, b, sh, sp, sq);
 }
 
 __global__ __launch_bounds__(kBlock) void k_cg_init(CgView c, const double* __restrict__ b)
@@ -98,6 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_finish(CgView c, double rtol
     const double bb = reduce_partials(c.part + c.nparts, c.nparts, sh);
     if (threadIdx.x == 0) {
         c.s->rz = rz;
+        c.s->rzk[0] = rz;
         c.s->bnorm2 = bb;
         c.s->rr = bb;
         c.s->beta = 0.0;
@@ -107,24 +163,47 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_finish(CgView c, double rtol
     }
 }
 
-// p_new = z + beta p_old and q = A p_new, partial p_new . q.  kNodeLanes
-// lanes per node; lane l takes neighbours l, l + kNodeLanes, ...; the three
-// row sums are then combined by a fixed shuffle tree.  p_old is read, p_new
-// written only for the node's own rows, so the two never alias.
-__global__ __launch_bounds__(kBlock) void k_cg_spmv(CgView c, int cur)
+// Iteration k, first launch.  For k > 0: r_k.z_k and r_k.r_k from the update's
+// partials; stop if converged or k reaches max_iter; beta = (r_k.z_k) /
+// (r_{k-1}.z_{k-1}).  Then p_new = z + beta p_old and q = A p_new, with the
+// partials of p_new . q.  kNodeLanes lanes per node; lane l takes neighbours
+// l, l + kNodeLanes, ...; the three row sums are combined by a fixed shuffle
+// tree.  p_old is read, p_new written only for the node's own rows, so the two
+// never alias.
+__global__ __launch_bounds__(kBlock) void k_cg_spmv(CgView c, int k, int cur, int max_iter)
 {
-    __shared__ double sh[kBlock];
+    __shared__ double sh[2 * kBlock];
     if (c.s->done)
         return;
-    const double beta = c.s->beta;
+    double beta = 0.0;
+    {
+        double rz = c.s->rzk[0], rr = c.s->rr;
+        if (k > 0)
+            reduce_partials2(c.part + c.nparts_s, c.part + c.nparts_s + c.nparts_u, c.nparts_u, sh, rz, rr);
+        if ((k > 0 && rr <= c.s->tol2) || k >= max_iter) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                c.s->rr = rr;
+                c.s->iters = k;
+                c.s->done = 1;
+            }
+            return;
+        }
+        if (k > 0) {
+            beta = rz / c.s->rzk[(k - 1) & 1];
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                c.s->rzk[k & 1] = rz;
+                c.s->rr = rr;
+                c.s->iters = k;
+            }
+        }
+    }
     const double* __restrict__ pold = c.p + (cur ? c.n : 0);
     double* __restrict__ pnew = c.p + (cur ? 0 : c.n);
     const int nn = c.n / 3;
     const int group = threadIdx.x / kNodeLanes, l = threadIdx.x & (kNodeLanes - 1);
     constexpr int kGroups = kBlock / kNodeLanes;
     double pq = 0.0;
-    // grid-stride over nodes (the grid is capped, which bounds the partials
-    // alpha adds); every group of a workgroup runs the same number of rounds
+    // grid-stride over nodes; every group of a workgroup runs the same number of rounds
     for (int base_node = blockIdx.x * kGroups; base_node < nn; base_node += gridDim.x * kGroups) {
         const int i = base_node + group;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
@@ -132,9 +211,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(CgView c, int cur)
             const int base = c.rowptr[3 * i];
             const int rl = c.rowptr[3 * i + 1] - base;
             const int deg = rl / 3;
-            for (int k = l; k < deg; k += kNodeLanes) {
-                const int j = c.colidx[base + 3 * k] / 3;
-                const double* v = c.vals + base + 3 * k;
+            for (int kk = l; kk < deg; kk += kNodeLanes) {
+                const int j = c.colidx[base + 3 * kk] / 3;
+                const double* v = c.vals + base + 3 * kk;
                 double pj[3];
 #pragma unroll
                 for (int q = 0; q < 3; ++q)
@@ -163,64 +242,39 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(CgView c, int cur)
             pq = pq + pr * q;
         }
     }
+    __syncthreads();  // sh is reused
     const double s = block_sum(pq, sh);
     if (threadIdx.x == 0)
         c.part[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_alpha(CgView c, int nparts)
+// Iteration k, second launch: alpha = (r_k.z_k) / (p.Ap) from the product's
+// partials; x += alpha p_new, r -= alpha q, z = Dinv r; partials of r.z and r.r
+// (grid-stride, each thread in ascending row order).
+__global__ __launch_bounds__(kBlock) void k_cg_update(CgView c, int k, int cur)
 {
-    __shared__ double sh[kBlock];
+    __shared__ double sh[2 * kBlock];
     if (c.s->done)
         return;
-    const double pq = reduce_partials(c.part, nparts, sh);
-    if (threadIdx.x == 0)
-        c.s->alpha = c.s->rz / pq;
-}
-
-// x += alpha p_new, r -= alpha q, z = Dinv r; partial r.z and r.r
-__global__ __launch_bounds__(kBlock) void k_cg_update(CgView c, int cur)
-{
-    __shared__ double sh[kBlock];
-    if (c.s->done)
-        return;
-    const double alpha = c.s->alpha;
+    const double pq = reduce_partials(c.part, c.nparts_s, sh);
+    const double alpha = c.s->rzk[k & 1] / pq;
     const double* __restrict__ pnew = c.p + (cur ? 0 : c.n);
-    const int i = blockIdx.x * kBlock + threadIdx.x;
     double rz = 0.0, rr = 0.0;
-    if (i < c.n) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < c.n; i += gridDim.x * kBlock) {
         c.x[i] = c.x[i] + alpha * pnew[i];
         const double r = c.r[i] - alpha * c.q[i];
         c.r[i] = r;
         const double z = r * c.dinv[i];
         c.z[i] = z;
-        rz = r * z;
-        rr = r * r;
+        rz = rz + r * z;
+        rr = rr + r * r;
     }
-    const double s1 = block_sum(rz, sh);
-    __syncthreads();
-    const double s2 = block_sum(rr, sh);
+    __syncthreads();  // sh is reused
+    double s1, s2;
+    block_sum2(rz, rr, sh, s1, s2);
     if (threadIdx.x == 0) {
-        c.part[blockIdx.x] = s1;
-        c.part[c.nparts + blockIdx.x] = s2;
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_cg_beta(CgView c, int max_iter)
-{
-    __shared__ double sh[kBlock];
-    if (c.s->done)
-        return;
-    const double rz = reduce_partials(c.part, c.nparts, sh);
-    __syncthreads();
-    const double rr = reduce_partials(c.part + c.nparts, c.nparts, sh);
-    if (threadIdx.x == 0) {
-        c.s->beta = rz / c.s->rz;
-        c.s->rz = rz;
-        c.s->rr = rr;
-        c.s->iters += 1;
-        if (rr <= c.s->tol2 || c.s->iters >= max_iter)
-            c.s->done = 1;
+        c.part[c.nparts_s + blockIdx.x] = s1;
+        c.part[c.nparts_s + c.nparts_u + blockIdx.x] = s2;
     }
 }
 
@@ -257,19 +311,26 @@ hipError_t launch_diag_positions(const DevView& v, int32_t* dpos, hipStream_t s)
     return hipGetLastError();
 }
 
-// Matrix-vector product grid: one workgroup per 16 nodes, at most 8192 (a
-// wider grid keeps more gathers in flight than fewer, longer-running groups).
+// Matrix-vector product grid: one workgroup per 16 nodes, at most
+// kSpmvGridMax; update grid: one per 256 rows, at most kUpdateGridMax.
 int spmv_grid(int n)
 {
     const int g = (int)blocks(n / 3, kBlock / kNodeLanes);
-    return g < 1 ? 1 : (g > 8192 ? 8192 : g);
+    return g < 1 ? 1 : (g > kSpmvGridMax ? kSpmvGridMax : g);
 }
 
-// Size of the partial-sum buffer: two vector-kernel halves or one SpMV grid.
+int update_grid(int n)
+{
+    const int g = (int)blocks(n, kBlock);
+    return g < 1 ? 1 : (g > kUpdateGridMax ? kUpdateGridMax : g);
+}
+
+// Size of the partial-sum buffer: the start kernels' two halves, or the
+// product's partials followed by the update's two halves.
 int cg_partials(int n)
 {
     const int a = 2 * (int)blocks(n, kBlock);
-    const int b = spmv_grid(n);
+    const int b = spmv_grid(n) + 2 * update_grid(n);
     return a > b ? a : b;
 }
 
@@ -280,16 +341,14 @@ hipError_t launch_cg_init(const CgView& c, const double* b, double rtol, hipStre
     return hipGetLastError();
 }
 
+// Iterations first .. first+count-1 (the solve launches k = 0 .. max_iter;
+// the product of k = max_iter only records the final residual).
 hipError_t launch_cg_iterations(const CgView& c, int first, int count, int max_iter, hipStream_t s)
 {
-    const unsigned gs = (unsigned)spmv_grid(c.n);
-    const unsigned gv = blocks(c.n, kBlock);
     for (int k = first; k < first + count; ++k) {
         const int cur = k & 1;  // which copy of p holds the previous direction
-        hipLaunchKernelGGL(k_cg_spmv, dim3(gs), dim3(kBlock), 0, s, c, cur);
-        hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(kBlock), 0, s, c, (int)gs);
-        hipLaunchKernelGGL(k_cg_update, dim3(gv), dim3(kBlock), 0, s, c, cur);
-        hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(kBlock), 0, s, c, max_iter);
+        hipLaunchKernelGGL(k_cg_spmv, dim3(c.nparts_s), dim3(kBlock), 0, s, c, k, cur, max_iter);
+        hipLaunchKernelGGL(k_cg_update, dim3(c.nparts_u), dim3(kBlock), 0, s, c, k, cur);
     }
     return hipGetLastError();
 }

@@ -152,11 +152,14 @@ struct DevView {
 struct CgScalars {
     double rz, alpha, beta, rr, bnorm2, tol2;
     int32_t iters, done;
+    double rzk[2];  // r_k . z_k by iteration parity (the product of iteration k reads k-1's, writes k's)
 };
 
 struct CgView {
     int32_t n;        // rows
-    int32_t nparts;   // partial sums per vector kernel (one per 256 rows)
+    int32_t nparts;   // partial sums of the start kernels (one per 256 rows)
+    int32_t nparts_s; // partial sums of the product (one per workgroup)
+    int32_t nparts_u; // partial sums of the update (one per workgroup, two dot products)
     const int32_t* rowptr;
     const int32_t* colidx;
     const double* vals;
@@ -264,6 +267,8 @@ hipError_t launch_slot_outer(int n_rows, const int32_t* rowptr, const int32_t* c
                              const double* b, double alpha, double* out, hipStream_t s);
 hipError_t launch_diag_positions(const DevView& v, int32_t* dpos, hipStream_t s);
 int cg_partials(int n);
+int spmv_grid(int n);
+int update_grid(int n);
 hipError_t launch_cg_init(const CgView& c, const double* b, double rtol, hipStream_t s);
 // Iterations first .. first+count-1 (the iteration index picks the copy of p).
 hipError_t launch_cg_iterations(const CgView& c, int first, int count, int max_iter, hipStream_t s);
