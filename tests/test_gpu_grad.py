@@ -75,6 +75,27 @@ def test_cg_matches_direct_solve():
     asm.close()
 
 
+def test_cg_iteration_limit():
+    """max_iter counts iterations exactly: 0 leaves x = 0 with relative residual 1; k < the
+    converged count stops after k iterations with the oracle PCG's k-th iterate (same
+    algorithm, other summation orders: close, not bitwise)."""
+    w, mask, f = small_case(3)
+    asm = build_at(w, mask)
+    pat = oracle.pattern(w.n_nodes, w.tets)
+    vals = asm.values().cpu().numpy()
+    fd = torch.from_numpy(f.reshape(-1)).cuda()
+    x0, it0, rr0 = asm.cg_solve(fd, rtol=1e-13, max_iter=0)
+    assert it0 == 0 and rr0 == 1.0 and not torch.any(x0)
+    _, full, _ = asm.cg_solve(fd, rtol=1e-13)
+    for k in (1, 5, full // 2):
+        xk, itk, rrk = asm.cg_solve(fd, rtol=1e-13, max_iter=k)
+        ok, oit, orr = oracle.pcg(pat[0], pat[1], vals, f.reshape(-1), rtol=1e-13, max_iter=k)
+        assert itk == k == oit and rrk > 1e-13
+        assert rel_err(xk.cpu().numpy(), ok) <= 1e-9, k
+        assert abs(rrk - orr) <= 1e-6 * orr
+    asm.close()
+
+
 def compliance_gradient(asm, f_dev, rtol=1e-13):
     u, it, rr = asm.cg_solve(f_dev, rtol=rtol)
     gA = asm.slot_outer(u, u, -1.0)
