@@ -229,6 +229,17 @@ def test_structural_counts():
     f = W.make_fracture(0, n=40)
     rp, ci = oracle.pattern(f.n_nodes, f.tets)
     assert (f.n_nodes, f.n_tets, len(ci)) == (68921, 384000, 8945649)
+    # the refinement superset: 48,000 parents + 8 red children each on the 41^3 node lattice;
+    # 591,101 node blocks (diagonal + off-diagonal), and corner nodes in 48 candidate tets
+    r = W.make_refinement(0, n=20, frames=1)
+    rp, ci = oracle.pattern(r.n_nodes, r.tets)
+    assert (r.n_nodes, r.n_tets, len(ci)) == (68921, 432000, 10019529)
+    t = r.tets.astype(np.int64)
+    deg = np.bincount(t.ravel(), minlength=r.n_nodes)
+    pairs = {(min(a, b), max(a, b)) for row in t for a, b in
+             ((row[0], row[1]), (row[0], row[2]), (row[0], row[3]), (row[1], row[2]), (row[1], row[3]), (row[2], row[3]))}
+    assert int(np.sum(deg > 0)) + len(pairs) == 591101
+    assert deg.max() == 48
 
 
 @pytest.mark.parametrize("seed", range(12))
