@@ -109,17 +109,36 @@ def load_traffic(kernel):
     return rec
 
 
-def load_frame_traffic():
+def load_frame_traffic(touched_kernel):
     """Per-frame HBM bytes of the two streaming kernels from the committed counter runs
-    (first pass over the headline step), or None if the kernel source changed since."""
+    (first pass over the headline step), or None if the kernel source changed since or the
+    counters were taken with another phase-2 instantiation than `touched_kernel`."""
     try:
         with open(TRAFFIC_FILE) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("source_sha") != source_sha():
+    if d.get("source_sha") != source_sha() or d.get("frames_touched_kernel") != touched_kernel:
         return None
     return d.get("frames")
+
+
+def kernel_instance(asm, kernel):
+    """Template instantiation of `kernel` that the context's mapping launches: the key of
+    its counter record (counters of another instantiation are not attached)."""
+    c = asm.get_config()
+    nt = "true" if c["rebuild_nt"] else "false"
+    if kernel == "k_element":
+        return f"k_element<{nt}>"
+    if kernel in ("k_reduce_all", "k_touched", "k_frame"):
+        which = "rebuild" if kernel == "k_reduce_all" else "stream"
+        qd, qo = c[which + "_qd"], c[which + "_qo"]
+        m = asm.bucket_map(which)
+        mixed = "true" if any(q != qd for q in m["diag"]) or any(q != qo for q in m["off"]) else "false"
+        if kernel == "k_reduce_all":
+            return f"k_reduce_all<{qd}, {qo}, {mixed}, {nt}>"
+        return f"{kernel}<{qd}, {qo}, {mixed}>"
+    return kernel
 
 
 def roofline(kernel, alg_bytes, seconds, launches, traffic_key=None, with_traffic=True):
@@ -231,7 +250,7 @@ class Stream:
         cands = [k for k in ("frame", "touched", "edits") if k in ktimes]
         dom = max(cands, key=lambda k: ktimes[k][1])
         return kern, roofline("k_" + dom, steps * per_step[dom], ktimes[dom][1] * 1e-3, ktimes[dom][0],
-                              with_traffic=self.headline)
+                              traffic_key=kernel_instance(self.asm, "k_" + dom), with_traffic=self.headline)
 
     def rebuild_roofline(self, reps=5):
         """Rebuild kernels timed with events at every frame's mask (the step returns to the start)."""
@@ -253,8 +272,10 @@ class Stream:
         eb = bytes_element(float(np.mean(act)), self.n_tets, self.n_nodes)
         n_e, ms_e = kt.get("element", (0, 0.0))
         n_r, ms_r = kt.get("reduce", (0, 0.0))
-        return {"element": roofline("k_element", eb * n_e, ms_e * 1e-3, n_e, with_traffic=self.headline),
-                "reduce": roofline("k_reduce_all", rb * n_r, ms_r * 1e-3, n_r, with_traffic=self.headline),
+        return {"element": roofline("k_element", eb * n_e, ms_e * 1e-3, n_e,
+                                    traffic_key=kernel_instance(asm, "k_element"), with_traffic=self.headline),
+                "reduce": roofline("k_reduce_all", rb * n_r, ms_r * 1e-3, n_r,
+                                   traffic_key=kernel_instance(asm, "k_reduce_all"), with_traffic=self.headline),
                 "rebuild_us_mean": round((ms_e + ms_r) * 1e3 / max(n_r, 1), 3),
                 "full_rebuild_alg_bytes": int(eb + rb)}
 
@@ -287,7 +308,7 @@ class Stream:
             return ev[0].elapsed_time(ev[1]) * 1e3
 
         rows, t_stream, t_cold, t_reb, t_reb_cold = [], [], [], [], []
-        ftr = load_frame_traffic() if self.headline else None
+        ftr = load_frame_traffic(kernel_instance(asm, "k_touched")) if self.headline else None
         for k, ((di, ds), st) in enumerate(zip(self.dframes, self.stats)):
             ids_h = self.frames_host[k][0]
             prev = torch.from_numpy(self.mask_before(k)[ids_h].copy()).cuda()  # undoes the frame

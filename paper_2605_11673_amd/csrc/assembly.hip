@@ -65,15 +65,26 @@ __device__ __forceinline__ void st2(double* p, double a, double b)
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
-// Remap so that each XCD takes runs of kXcdRun consecutive workgroups in turn:
-// within a run neighbouring blocks share contribution, descriptor and CSR
-// cache lines, and the runs spread every part of the work (the diagonal
-// blocks, then the off-diagonal ones) evenly over the XCDs.  One contiguous
-// range per XCD put the whole diagonal section on three XCDs and was 4% slower
-// in the reduce; plain round-robin was 1% slower.  Workgroups past the last
-// whole round of runs keep their ids, so the map is a permutation of [0, G).
-constexpr int kXcdRun = 16;
+// The rebuild kernels remap workgroup ids so that neighbouring work, which
+// shares contribution, descriptor and CSR cache lines, runs on one XCD.
+//
+// Element kernel: each XCD walks one contiguous eighth of the tets.
 __device__ __forceinline__ int xcd_remap(int wg, int G)
+{
+    const int q = G / kXcds, r = G % kXcds;
+    const int x = wg % kXcds, idx = wg / kXcds;
+    const int base = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+    return base + idx;
+}
+
+// Reduce: each XCD takes runs of kXcdRun consecutive workgroups in turn, so
+// that the runs spread every part of the work (the diagonal blocks, then the
+// off-diagonal ones) evenly over the XCDs.  One contiguous range per XCD put
+// the whole diagonal section on three XCDs and was 4% slower; plain
+// round-robin was 1% slower.  Workgroups past the last whole round of runs
+// keep their ids, so the map is a permutation of [0, G).
+constexpr int kXcdRun = 16;
+__device__ __forceinline__ int xcd_remap_runs(int wg, int G)
 {
     const int full = G / (kXcds * kXcdRun) * (kXcds * kXcdRun);
     if (wg >= full)
@@ -483,7 +494,7 @@ __device__ __forceinline__ void off_value_rows(const DevView& v, const BlockDesc
 template <int QD, int QO, bool MIXED, bool NT>
 __global__ __launch_bounds__(kBlock) void k_reduce_all(DevView v, int64_t diag_lanes, MapConfig m)
 {
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int wg = xcd_remap_runs(blockIdx.x, gridDim.x);
     const int64_t t = (int64_t)wg * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
     if (t < diag_lanes) {
