@@ -248,6 +248,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_element(DevView v, const dou
 }
 
 // dL/dx of node i, component c: its diagonal segment's xbar in ascending tet id.
+// Terms are loaded kChunk at a time and then added in order, so that a
+// segment costs a few memory round trips instead of one per term.
 __global__ __launch_bounds__(kBlock) void k_adjoint_nodes(DevView v, const double* __restrict__ xbar,
                                                           double* __restrict__ g_x)
 {
@@ -259,8 +261,17 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_nodes(DevView v, const doubl
     double acc = 0.0;
     if (b >= 0) {
         const BlockDesc d = v.desc[b];
-        for (int k = d.k0; k < d.k1; ++k)
-            acc = acc + xbar[3 * (size_t)k + c];
+        constexpr int kChunk = 8;
+        for (int k0 = d.k0; k0 < d.k1; k0 += kChunk) {
+            double x[kChunk];
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j)
+                x[j] = k0 + j < d.k1 ? xbar[3 * (size_t)(k0 + j) + c] : 0.0;
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j)
+                if (k0 + j < d.k1)
+                    acc = acc + x[j];
+        }
     }
     g_x[t] = acc;
 }

@@ -56,7 +56,9 @@ __global__ __launch_bounds__(kBlock) void k_tet_mass(DevView v, double* __restri
 }
 
 // One thread per node: its diagonal block's incidence segment in ascending
-// tet id, active terms only.
+// tet id, active terms only.  Tet ids, mask bytes and masses are loaded
+// kChunk at a time and then added in order (a few memory round trips per
+// segment instead of two per term).
 __global__ __launch_bounds__(kBlock) void k_lumped_mass(DevView v, const int32_t* __restrict__ dinc,
                                                         const double* __restrict__ ml, double* __restrict__ m)
 {
@@ -67,10 +69,23 @@ __global__ __launch_bounds__(kBlock) void k_lumped_mass(DevView v, const int32_t
     const int b = v.ndiag[i];
     if (b >= 0) {
         const BlockDesc d = v.desc[b];
-        for (int k = d.k0; k < d.k1; ++k) {
-            const int e = dinc[k];
-            if (v.mask[e])
-                acc = acc + ml[e];
+        constexpr int kChunk = 8;
+        for (int k0 = d.k0; k0 < d.k1; k0 += kChunk) {
+            int e[kChunk];
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j)
+                e[j] = k0 + j < d.k1 ? dinc[k0 + j] : -1;
+            bool on[kChunk];
+            double w[kChunk];
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) {
+                on[j] = e[j] >= 0 && v.mask[e[j]];
+                w[j] = e[j] >= 0 ? ml[e[j]] : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j)
+                if (on[j])
+                    acc = acc + w[j];
         }
     }
     m[3 * (size_t)i + 0] = acc;
