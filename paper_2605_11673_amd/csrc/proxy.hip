@@ -84,6 +84,9 @@ __device__ __forceinline__ double off_value(int32_t count)
     return count > 0 ? -1.0 : 0.0;
 }
 
+// Segment and row loops load this many terms before using any of them.
+constexpr int kChunk = 8;
+
 // Rebuild, step 1: every edge's count from the mask over its incidence
 // segment (eq. (1)), and its two off-diagonal entries (eqs. (2), (3)).
 __global__ __launch_bounds__(kBlock) void k_proxy_counts(ProxyView v)
@@ -93,8 +96,15 @@ __global__ __launch_bounds__(kBlock) void k_proxy_counts(ProxyView v)
         return;
     int32_t cnt = 0;
     const int k1 = v.eseg[e + 1];
-    for (int k = v.eseg[e]; k < k1; ++k)
-        cnt += v.mask[v.einc[k]];
+    for (int k0 = v.eseg[e]; k0 < k1; k0 += kChunk) {  // loads in flight together
+        int t[kChunk];
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j)
+            t[j] = k0 + j < k1 ? v.einc[k0 + j] : -1;
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j)
+            cnt += t[j] >= 0 ? v.mask[t[j]] : 0;
+    }
     v.c[e] = cnt;
     const double x = off_value(cnt);
     v.values[v.epos[2 * e]] = x;
@@ -113,8 +123,15 @@ __global__ __launch_bounds__(kBlock) void k_proxy_diagonal(ProxyView v)
         return;
     int32_t d = 0;
     const int k1 = v.rowptr[u + 1];
-    for (int k = v.rowptr[u]; k < k1; ++k)
-        d += (k != p && v.values[k] == -1.0) ? 1 : 0;
+    for (int k0 = v.rowptr[u]; k0 < k1; k0 += kChunk) {  // loads in flight together
+        double x[kChunk];
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j)
+            x[j] = k0 + j < k1 ? v.values[k0 + j] : 0.0;
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j)
+            d += (k0 + j < k1 && k0 + j != p && x[j] == -1.0) ? 1 : 0;
+    }
     v.deg[u] = d;
     v.values[p] = (double)d + v.eps;
 }
