@@ -338,9 +338,12 @@ sta_status sta_latency_probe(void* stream, double* out4);
 
 /* Measured streaming bandwidth of this GPU's HBM, in GB/s (1e9 B/s), on
  * `stream`: out3[0] reading 1 GiB, out3[1] writing 1 GiB, out3[2] copying
- * 1 GiB (2 GiB moved), 16-byte accesses by consecutive lanes, averaged over
- * ten launches after one warm-up.  Allocates and frees 2 GiB of device
- * memory; synchronises `stream`.  The achieved fractions of the rebuild
+ * 1 GiB (2 GiB moved), 16-byte accesses by consecutive lanes in a
+ * grid-stride loop; each kind is timed over ten launches after one warm-up at
+ * grids of 1,024, 4,096, 16,384 and 65,536 workgroups of 256 lanes, and the
+ * best grid is reported (writes are fastest with many short-lived
+ * workgroups, reads and copies with few).  Allocates and frees 2 GiB of
+ * device memory; synchronises `stream`.  The achieved fractions of the rebuild
  * kernels are reported against the published 8 TB/s peak; these numbers
  * say what a plain streaming kernel reaches on the same device. */
 sta_status sta_bandwidth_probe(void* stream, double* out3);

@@ -168,7 +168,7 @@ extern "C" sta_status sta_bandwidth_probe(void* stream, double* out3)
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t bytes = 1ll << 30;  // per buffer, far beyond the 256 MB Infinity Cache
     const int64_t n = bytes / 16;
-    const unsigned grid = 8192;
+    const unsigned grids[4] = {1024, 4096, 16384, 65536};
     const int reps = 10;
     dvec2 *a = nullptr, *b = nullptr;
     double* dout = nullptr;
@@ -180,27 +180,32 @@ extern "C" sta_status sta_bandwidth_probe(void* stream, double* out3)
     if (e == hipSuccess) e = hipEventCreate(&e1);
     double res[3] = {0, 0, 0};
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_bw_write, dim3(grid), dim3(256), 0, s, a, n);
-        hipLaunchKernelGGL(k_bw_write, dim3(grid), dim3(256), 0, s, b, n);
+        hipLaunchKernelGGL(k_bw_write, dim3(grids[0]), dim3(256), 0, s, a, n);
+        hipLaunchKernelGGL(k_bw_write, dim3(grids[0]), dim3(256), 0, s, b, n);
         e = hipGetLastError();
     }
     for (int which = 0; which < 3 && e == hipSuccess; ++which) {
-        for (int r = -1; r < reps && e == hipSuccess; ++r) {  // r = -1: warm-up
-            if (r == 0) e = hipEventRecord(e0, s);
-            if (which == 0)
-                hipLaunchKernelGGL(k_bw_read, dim3(grid), dim3(256), 0, s, a, n, dout);
-            else if (which == 1)
-                hipLaunchKernelGGL(k_bw_write, dim3(grid), dim3(256), 0, s, b, n);
-            else
-                hipLaunchKernelGGL(k_bw_copy, dim3(grid), dim3(256), 0, s, a, b, n);
-            if (e == hipSuccess) e = hipGetLastError();
+        for (int gi = 0; gi < 4 && e == hipSuccess; ++gi) {
+            const dim3 grid(grids[gi]);
+            for (int r = -1; r < reps && e == hipSuccess; ++r) {  // r = -1: warm-up
+                if (r == 0) e = hipEventRecord(e0, s);
+                if (which == 0)
+                    hipLaunchKernelGGL(k_bw_read, grid, dim3(256), 0, s, a, n, dout);
+                else if (which == 1)
+                    hipLaunchKernelGGL(k_bw_write, grid, dim3(256), 0, s, b, n);
+                else
+                    hipLaunchKernelGGL(k_bw_copy, grid, dim3(256), 0, s, a, b, n);
+                if (e == hipSuccess) e = hipGetLastError();
+            }
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            const double moved = (double)bytes * (which == 2 ? 2 : 1) * reps;
+            const double gbs = ms > 0.0f ? moved / (ms * 1e-3) / 1e9 : 0.0;
+            if (gbs > res[which])
+                res[which] = gbs;
         }
-        if (e == hipSuccess) e = hipEventRecord(e1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        const double moved = (double)bytes * (which == 2 ? 2 : 1) * reps;
-        res[which] = moved / (ms * 1e-3) / 1e9;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
