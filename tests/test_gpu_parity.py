@@ -104,6 +104,30 @@ def test_fracture_full_size_every_frame():
     asm.close()
 
 
+@pytest.mark.parametrize("seed", [1, 2])
+def test_fracture_full_size_other_seeds(seed):
+    """The full-size fracture+merge stream for two more seeds (other jitter, moduli,
+    Voronoi sites and impact point, so other straddler sets and frame contents): every
+    frame bitwise equal to the oracle, and the GPU rebuild at the end."""
+    S = stafem()
+    w = W.make_fracture(seed)
+    frames = list(w.frames) + W.merge_stream(w.frames)
+    print(f"[parity] fracture 40^3 seed {seed}: {sum(len(f[0]) for f in frames)} edits", flush=True)
+    pat = oracle.pattern(w.n_nodes, w.tets)
+    asm = S.Assembler.from_workload(w)
+    mask = w.mask0.copy()
+    for t, (ids, st) in enumerate(frames):
+        mask[ids] = st
+        asm.apply_edits(*S.upload_frame(ids, st))
+        assert_bitwise(gpu_values(asm), oracle.rebuild_workload(w, mask, pat), f"seed {seed} frame {t}")
+    got = gpu_values(asm)
+    asm.full_rebuild()
+    assert_bitwise(gpu_values(asm), got, f"seed {seed} final rebuild")
+    assert np.all(mask == 1)
+    assert asm.status_sync() == S.STA_OK
+    asm.close()
+
+
 def test_fracture_full_size_tuned_configuration():
     """The configuration the benchmark times: the autotuner's choice on the peak frame
     (as bench.py makes it), then the 48-frame fracture+merge stream, every frame bitwise
