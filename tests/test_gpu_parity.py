@@ -158,6 +158,14 @@ def test_refinement_full_size():
     asm.close()
 
 
+def test_refinement_full_size_second_seed():
+    """The refinement superset with another seed (other jitter, moduli and choice of
+    refined parents): every frame of the refine and merge stream bitwise equal to the oracle."""
+    w = W.make_refinement(1)
+    asm, mask, pat = run_stream(w, label="refine 20^3 seed 1")
+    asm.close()
+
+
 def test_edit_semantics_and_rollback():
     S = stafem()
     w = W.make_cube(3)
