@@ -184,6 +184,28 @@ def test_face_full_size_with_bfs_spot_checks():
     asm.close()
 
 
+@pytest.mark.parametrize("seed", [1, 2])
+def test_both_adjacencies_full_size_other_seeds(seed):
+    """40^3 fracture+merge stream for two more seeds: face labels against the oracle at
+    every frame, vertex labels every sixth frame, and the component counts' course."""
+    Sm = S()
+    w = W.make_fracture(seed=seed)
+    frames = list(w.frames) + W.merge_stream(w.frames)
+    pairs = C.face_pairs(w.tets)
+    asm = Sm.Assembler.from_workload(w)
+    mask = w.mask0.copy()
+    ks = []
+    for t, (ids, st) in enumerate(frames):
+        asm.apply_edits(*Sm.upload_frame(ids, st))
+        mask[ids] = st
+        ks.append(check_face(asm, w, mask, pairs, f"seed {seed} frame {t}")[1])
+        if t % 6 == 5:
+            check(asm, w, mask, f"seed {seed} frame {t} (vertex)")
+    print(f"[connect] seed {seed} face components along the stream: {ks}", flush=True)
+    assert ks[-1] == 1 and np.all(mask == 1)
+    asm.close()
+
+
 def test_face_refinement_and_batch():
     """Refinement superset: hanging-node interfaces separate refined regions (many more
     face components than vertex components); a batch of disjoint cubes: one component per
