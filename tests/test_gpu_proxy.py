@@ -104,11 +104,13 @@ def test_random_small_meshes(seed):
     px.close()
 
 
-def test_fracture_full_size_every_frame():
+@pytest.mark.parametrize("seed", [0, 1])
+def test_fracture_full_size_every_frame(seed):
     """40^3 cube (384,000 tets, 462,520 edges): 24 Voronoi fracture frames (50..2000
-    deletions) then their reinsertion, every frame bitwise against the oracle."""
-    w = W.make_fracture(seed=0)
-    px, _, _ = run_stream(w, list(w.frames) + W.merge_stream(w.frames), label="fracture 40")
+    deletions) then their reinsertion, every frame bitwise against the oracle, for two
+    seeds (other jitter, sites and impact point)."""
+    w = W.make_fracture(seed=seed)
+    px, _, _ = run_stream(w, list(w.frames) + W.merge_stream(w.frames), label=f"fracture 40 seed {seed}")
     px.close()
 
 
