@@ -7,7 +7,6 @@ oracle's values bit for bit, in the rebuild and in every streaming frame.
 The refinement superset has diagonal blocks in all three buckets (coarse
 corner nodes carry 48 candidate tets); the cube has none above 24.
 """
-import itertools
 
 import numpy as np
 import pytest
