@@ -71,6 +71,23 @@ def bytes_frame(st):
     return bytes_edits(st) + bytes_touched(st)
 
 
+def bytes_delta(st):
+    """+/- delta frame (k_delta_edits + k_delta_clear): per edit its id, state, tet stamp
+    read/write and mask read, and its stamp cleared again (20 B); per changed tet its
+    512-byte record, its mask write, and the 144 CSR entries of its 10 blocks read and
+    written by the atomic additions (2,817 B)."""
+    return 20 * st["edits"] + 2817 * st["changed"]
+
+
+def bytes_connectivity_pass(n_tets, n_nodes, n_pairs=0):
+    """A lower bound for one connectivity rebuild: every tet's mask byte, vertex ids (16 B,
+    vertex adjacency) and label (4 B), every node's parent (4 B), and for face adjacency
+    every candidate pair (8 B) with its two mask bytes; one pass over the data."""
+    if n_pairs:
+        return 5 * n_tets + 10 * n_pairs
+    return 21 * n_tets + 4 * n_nodes
+
+
 def bytes_element(n_active, n_tets, n_nodes):
     """Rebuild element kernel: per tet its mask byte, 10 incidence positions and 78
     contribution doubles written (element matrix or zeros: 665 B); per active tet its
@@ -553,7 +570,7 @@ def apply_config(asm, cfg):
         asm.set_bucket_map(k, m["diag"], m["off"])
 
 
-def delta_section(torch, stafem, w, frames, cfg, exact_step_s, args):
+def delta_section(torch, stafem, w, frames, cfg, exact_step_s, args, stats=None, oracle_s_per_frame=None):
     """The paper's +/- delta policy (sta_apply_edits_delta) on the headline stream and on a
     repeated-locality stream (one slab deleted and reinserted frame after frame): time per
     frame against the exact policy, and the drift from the rebuild after many frames."""
@@ -573,6 +590,21 @@ def delta_section(torch, stafem, w, frames, cfg, exact_step_s, args):
            "exact_us_per_frame": round(exact_step_s * 1e6 / len(frames), 3),
            "exact_over_delta": round(exact_step_s / step_s, 3),
            "drift_after_frames": n_frames, "drift": dr}
+    if stats:
+        # kernel events over one host-launched pass of the step (the same frames)
+        asm.enable_kernel_timing(True)
+        asm.kernel_times()
+        delta_step()
+        kt = asm.kernel_times()
+        asm.enable_kernel_timing(False)
+        n_d, ms_d = kt.get("delta", (0, 0.0))
+        out["roofline"] = roofline("k_delta_edits+k_delta_clear", sum(bytes_delta(st) for st in stats),
+                                   ms_d * 1e-3, n_d, with_traffic=False)
+    if oracle_s_per_frame:
+        out["cpu_baseline"] = {"value": round(oracle_s_per_frame * 1e6, 1), "unit": "us per frame", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "the oracle's rebuild from the mask, against which the delta policy's "
+                                         "drift is bounded (the headline CPU-baseline measurement)"}
     # repeated locality: the peak frame's tets (a slab near the impact point) deleted and
     # reinserted on alternate frames
     peak = int(np.argmax([len(f[0]) for f in frames[:24]]))
@@ -604,6 +636,9 @@ def delta_section(torch, stafem, w, frames, cfg, exact_step_s, args):
                        "drift_after_frames": reps * len(cycle), "drift": drift(torch, asm)}
     assert asm.status_sync() == stafem.STA_OK
     asm.close()
+    if "roofline" in out:
+        log(f"[bench] delta kernels: {out['roofline']['avg_launch_us']} us per frame, "
+            f"{out['roofline']['frac'] * 100:.1f}% of HBM peak")
     log(f"[bench] delta: {out['delta_us_per_frame']} us/frame (exact {out['exact_us_per_frame']}), drift "
         f"{dr['max_abs']:.3e}; locality {out['locality']['delta_us_per_frame']} vs "
         f"{out['locality']['exact_us_per_frame']} us/frame, drift {out['locality']['drift']['max_abs']:.3e}")
@@ -619,9 +654,11 @@ def euler_section(torch, stafem, workloads, w, frames, cfg, args, rtol=1e-8):
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     res = {}
     traj = {}
+    cg = {}
     for policy in ("stream", "rebuild"):
         asm = stafem.Assembler.from_workload(w)
         apply_config(asm, cfg)
+        asm.kernel_times()
         u = torch.zeros(asm.n_rows, dtype=torch.float64, device="cuda")
         v = torch.zeros_like(u)
         upd, sol, its = [], [], []
@@ -633,7 +670,9 @@ def euler_section(torch, stafem, workloads, w, frames, cfg, args, rtol=1e-8):
             if policy == "rebuild":
                 asm.full_rebuild()
             ev[1].record()
+            asm.enable_kernel_timing(True)  # the CG chunks, timed by events (both policies alike)
             it, _ = asm.euler_step(u, v, f, rtol=rtol)
+            asm.enable_kernel_timing(False)
             ev[2].record()
             ev[2].synchronize()
             upd.append(ev[0].elapsed_time(ev[1]) * 1e3)
@@ -641,6 +680,8 @@ def euler_section(torch, stafem, workloads, w, frames, cfg, args, rtol=1e-8):
             its.append(it)
         torch.cuda.synchronize()
         traj[policy] = (u.clone(), v.clone())
+        kt = asm.kernel_times()
+        cg[policy] = (kt.get("solve", (0, 0.0))[1], int(np.sum(its)), asm.n_rows, asm.nnz)
         assert asm.status_sync() == stafem.STA_OK
         asm.close()
         res[policy] = {"update_us_mean": round(float(np.mean(upd)), 3),
@@ -655,6 +696,28 @@ def euler_section(torch, stafem, workloads, w, frames, cfg, args, rtol=1e-8):
            "update_speedup_stream_vs_rebuild": round(res["rebuild"]["update_us_mean"] / res["stream"]["update_us_mean"],
                                                      2),
            "trajectories_bitwise_equal": bool(same)}
+    ms_cg, it_cg, n_rows, nnz = cg["stream"]
+    out["roofline"] = roofline("cg_iteration", bytes_cg_iteration(n_rows, nnz) * it_cg, ms_cg * 1e-3, it_cg,
+                               with_traffic=False)
+    if not args.no_cpu_baseline:
+        # the oracle's step of eq. (9) at the frame-12 state: its matrix, lumped mass and PCG
+        import oracle
+        mask = w.mask0.copy()
+        for ids, st in frames[:13]:
+            mask[ids] = st
+        pat = oracle.pattern(w.n_nodes, w.tets)
+        fh = f.cpu().numpy()
+        t0 = time.perf_counter()
+        vals = oracle.rebuild(w.x, w.tets, w.E, w.nu, w.rho, w.dt, mask, *pat)
+        m = oracle.lumped_mass(w.x, w.tets, w.rho, mask)
+        _, _, it_o, _ = oracle.euler_step(*pat, vals, m, np.zeros_like(fh), np.zeros_like(fh), fh, w.dt, rtol=rtol)
+        t_o = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(t_o * 1e6, 1), "unit": "us per frame", "cores": 1, "kind": "oracle",
+                               "sample": f"one step at the frame-12 state from rest (oracle matrix, lumped mass "
+                                         f"and PCG, {it_o} iterations), single-threaded"}
+    log(f"[bench] euler: CG {out['roofline']['avg_launch_us']} us per iteration "
+        f"({out['roofline']['frac'] * 100:.1f}% of HBM peak)"
+        + (f"; oracle step {out['cpu_baseline']['value'] * 1e-6:.2f} s" if "cpu_baseline" in out else ""))
     log(f"[bench] euler: stream frame {res['stream']['frame_us_mean']} us (update {res['stream']['update_us_mean']}), "
         f"rebuild frame {res['rebuild']['frame_us_mean']} us (update {res['rebuild']['update_us_mean']}), "
         f"CG {res['stream']['cg_iterations_mean']} it, same trajectory {same}")
@@ -780,15 +843,42 @@ def connectivity_section(torch, stafem, w, frames, args):
             again, k = asm.components(adj)
             r["stable"] = r["stable"] and bool(torch.equal(again, lab))
             r["counts"].append(k)
+    n_pairs = 0  # candidate face pairs, counted in the CPU-baseline leg
     asm.close()
     out = {"workload": "components of the active tets rebuilt after every frame of the headline stream, "
                        "shared-vertex and shared-face adjacency"}
+    oracle_s = {}
+    if not args.no_cpu_baseline:
+        # the oracle's components at the peak frame's mask (library connected_components)
+        from oracle import connectivity as C
+        mask = w.mask0.copy()
+        for ids, st in frames[:13]:
+            mask[ids] = st
+        t0 = time.perf_counter()
+        C.components(w.n_nodes, w.tets, mask)
+        oracle_s["vertex"] = time.perf_counter() - t0
+        pairs = C.face_pairs(w.tets)
+        n_pairs = len(pairs)
+        t0 = time.perf_counter()
+        C.face_components(w.tets, mask, pairs)
+        oracle_s["face"] = time.perf_counter() - t0
     for adj, r in res.items():
         c = r["counts"]
-        out[adj] = {"rebuild_us_median": round(float(np.median(r["times"])), 3),
+        med = float(np.median(r["times"]))
+        out[adj] = {"rebuild_us_median": round(med, 3),
                     "rebuild_us_max": round(float(np.max(r["times"])), 3),
                     "components_initial": c[0], "components_max": int(max(c)), "components_final": c[-1],
                     "repeat_labels_identical": r["stable"]}
+        if adj == "vertex" or n_pairs:
+            nb = bytes_connectivity_pass(w.n_tets, w.n_nodes, n_pairs if adj == "face" else 0)
+            out[adj]["roofline"] = roofline(f"connectivity ({adj}), one-pass lower bound", nb, med * 1e-6, 1,
+                                            with_traffic=False)
+        if adj in oracle_s:
+            out[adj]["cpu_baseline"] = {"value": round(oracle_s[adj] * 1e6, 1), "unit": "us per rebuild",
+                                        "cores": 1, "kind": "oracle",
+                                        "sample": "components at the frame-12 mask (library connected_components"
+                                                  + (" over the candidate face pairs, pairs found beforehand)"
+                                                     if adj == "face" else " over the vertex graph)")}
         log(f"[bench] connectivity ({adj}): {out[adj]['rebuild_us_median']} us per rebuild, components "
             f"{c[0]} -> {max(c)} -> {c[-1]}")
     return out
@@ -883,7 +973,8 @@ def main():
     if not args.quick and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, w, frames, stats)
     if not args.quick and not args.no_extras:
-        out["delta"] = delta_section(torch, stafem, w, frames, out["tuned_config"], step_s, args)
+        out["delta"] = delta_section(torch, stafem, w, frames, out["tuned_config"], step_s, args, stats,
+                                     out.get("cpu_baseline", {}).get("rebuild_s_per_frame"))
         out["proxy"] = proxy_section(torch, stafem, w, frames, args)
         out["euler"] = euler_section(torch, stafem, workloads, w, frames, out["tuned_config"], args)
         out["connectivity"] = connectivity_section(torch, stafem, w, frames, args)
