@@ -10,7 +10,8 @@
 //
 // Vertex adjacency: components are found over the vertices by
 // hooking roots and shortcutting (a Shiloach-Vishkin style iteration): every
-// vertex keeps a parent pointer f, initially itself; in a hooking pass each
+// vertex keeps a parent pointer f, initially the smallest vertex of its
+// active tets (itself if smaller or isolated); in a hooking pass each
 // active tet climbs from its four vertices to their roots and lowers the
 // larger roots (and the vertices) to the smallest one with atomic minimum; a
 // shortcut pass points every vertex at the root it reaches.  Pointers only
@@ -41,13 +42,44 @@ unsigned blocks(int64_t n)
 }
 
 // flag[0]: changed in this pass; flag[1]: number of components
-__global__ __launch_bounds__(kBlock) void k_cc_init(int n_nodes, int* f, uint32_t* mark)
+
+// Seed (replaces the identity start): every vertex points at the smallest
+// vertex of its active tets, or at itself if that is smaller or it has none,
+// read from its diagonal incidence segment (dinc: the tet of each incidence).
+// That vertex shares a tet with it, so the pointer stays inside the component
+// and only decreases, as every later update does; the hooking passes then
+// start from local minima and contend far less on their atomics.
+__global__ __launch_bounds__(kBlock) void k_cc_seed(DevView v, const int32_t* __restrict__ dinc, int* f,
+                                                    uint32_t* mark)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n_nodes) {
-        f[i] = i;
-        mark[i] = 0u;
+    if (i >= v.n_nodes)
+        return;
+    int m = i;
+    const int b = v.ndiag[i];
+    if (b >= 0) {
+        const BlockDesc d = v.desc[b];
+        constexpr int kChunk = 8;
+        for (int k0 = d.k0; k0 < d.k1; k0 += kChunk) {
+            int e[kChunk];
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j)
+                e[j] = k0 + j < d.k1 ? dinc[k0 + j] : -1;
+            bool on[kChunk];
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j)
+                on[j] = e[j] >= 0 && v.mask[e[j]];
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j)
+                if (on[j]) {
+                    const int4 t = v.T[e[j]];
+                    const int lo = min(min(t.x, t.y), min(t.z, t.w));
+                    m = lo < m ? lo : m;
+                }
+        }
     }
+    f[i] = m;
+    mark[i] = 0u;
 }
 
 // Follow parent pointers from x towards its root (at most kMaxSteps hops:
@@ -295,11 +327,11 @@ hipError_t run_face_components(const DevView& v, const int2* pairs, int64_t n_pa
 
 // Component labels into label (device, n_tets); *n_components on the host.
 // Synchronises s.  Returns hipErrorUnknown if the iteration bound is hit.
-hipError_t run_components(const DevView& v, int* f, uint32_t* mark, uint32_t* flag, uint32_t* host_flag,
-                          int32_t* label, int64_t* n_components, int* passes, hipStream_t s)
+hipError_t run_components(const DevView& v, const int32_t* dinc, int* f, uint32_t* mark, uint32_t* flag,
+                          uint32_t* host_flag, int32_t* label, int64_t* n_components, int* passes, hipStream_t s)
 {
     const unsigned gn = v.n_nodes > 0 ? blocks(v.n_nodes) : 1u;
-    hipLaunchKernelGGL(k_cc_init, dim3(gn), dim3(kBlock), 0, s, v.n_nodes, f, mark);
+    hipLaunchKernelGGL(k_cc_seed, dim3(gn), dim3(kBlock), 0, s, v, dinc, f, mark);
     hipError_t e = hipGetLastError();
     *passes = 0;
     // hooking passes until one changes nothing (then its reads were exact, so
@@ -383,7 +415,7 @@ extern "C" sta_status sta_components(sta_ctx* ctx, int32_t* labels_dev, int64_t*
     uint32_t* mark = reinterpret_cast<uint32_t*>(ctx->cc_ws + n);
     uint32_t* flag = mark + n;
     int64_t k = 0;
-    e = run_components(ctx->v, f, mark, flag, ctx->cc_host, labels_dev, &k, &ctx->cc_passes, s);
+    e = run_components(ctx->v, ctx->dinc, f, mark, flag, ctx->cc_host, labels_dev, &k, &ctx->cc_passes, s);
     if (e == hipErrorUnknown) {
         ctx->errmsg = "connectivity: pass bound exceeded (labels invalid)";
         return STA_EHIP;
