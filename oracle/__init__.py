@@ -30,7 +30,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 
-CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC", "-shared"]
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC", "-shared", "-fopenmp"]
 
 
 def build(force: bool = True) -> str:
@@ -66,6 +66,9 @@ def lib():
         L.oracle_rebuild_weighted.argtypes = [_i64, _d, _i64, _i32, _d, ctypes.c_double, ctypes.c_double,
                                               ctypes.c_double, _d, ctypes.c_int, _i32, _i32, _i64, _d]
         L.oracle_rebuild_weighted.restype = ctypes.c_int
+        L.oracle_rebuild_rows.argtypes = [_i64, _d, _i64, _i32, _d, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, _u8, _i32, _i32, _d, ctypes.POINTER(ctypes.c_int)]
+        L.oracle_rebuild_rows.restype = ctypes.c_int
         L.oracle_lumped_mass.argtypes = [_i64, _d, _i64, _i32, ctypes.c_double, _u8, _d]
         L.oracle_lumped_mass.restype = None
         L.oracle_dense.argtypes = [_i64, _d, _i64, _i32, _d, ctypes.c_double, ctypes.c_double,
@@ -127,6 +130,22 @@ def rebuild(x, tets, E, nu, rho, dt, mask, rowptr, colidx) -> np.ndarray:
     if rc != 0:
         raise RuntimeError(f"oracle_rebuild failed ({rc}): pattern lacks an entry")
     return vals
+
+
+def rebuild_rows(x, tets, E, nu, rho, dt, mask, rowptr, colidx):
+    """The rebuild of ``rebuild`` computed row by row on all host threads (OpenMP; the
+    thread count follows OMP_NUM_THREADS).  Same terms in the same order per slot, so
+    the values are bitwise those of ``rebuild``.  Returns (values, threads used)."""
+    x, tets, E, mask = _f64(x), _i32a(tets), _f64(E), _u8a(mask)
+    rowptr, colidx = _i32a(rowptr), _i32a(colidx)
+    vals = np.empty(int(rowptr[-1]))
+    th = ctypes.c_int(0)
+    rc = lib().oracle_rebuild_rows(x.shape[0], _p(x, _d), tets.shape[0], _p(tets, _i32), _p(E, _d),
+                                   float(nu), float(rho), float(dt), _p(mask, _u8),
+                                   _p(rowptr, _i32), _p(colidx, _i32), _p(vals, _d), ctypes.byref(th))
+    if rc != 0:
+        raise RuntimeError(f"oracle_rebuild_rows failed ({rc})")
+    return vals, int(th.value)
 
 
 def rebuild_weighted(x, tets, E, nu, rho, dt, weights, rowptr, colidx, count_only=False) -> np.ndarray:

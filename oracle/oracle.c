@@ -28,6 +28,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_OK 0
 #define OR_ENOSLOT (-1)
@@ -196,6 +199,87 @@ int oracle_rebuild_weighted(int64_t n_nodes, const double *x, int64_t n_tets, co
                 values[s] = values[s] + (count_only ? w[e] : w[e] * fabs(A[r * 12 + c]));
             }
     }
+    return OR_OK;
+}
+
+/* The same rebuild as oracle_rebuild, row by row on all host threads (a CPU
+ * baseline on many cores, not a second definition).  Each slot (row 3i+p,
+ * column 3j+q) is written by exactly one thread: +0.0, then, over the active
+ * tets that hold node i in ascending id, the term A_e[3a+p][3b+q] of those
+ * that also hold node j (a, b: the local vertices of i and j).  These are
+ * the same terms in the same order as the element-major scatter, so the
+ * values are bitwise those of oracle_rebuild.  Element matrices of the
+ * active tets are computed first (one per tet, in parallel) into scratch
+ * the routine allocates.  *threads_out (may be NULL) receives the number of
+ * threads used.  Returns OR_ENOMEM if scratch cannot be allocated. */
+int oracle_rebuild_rows(int64_t n_nodes, const double *x, int64_t n_tets, const int32_t *tets,
+                        const double *E, double nu, double rho, double dt, const uint8_t *mask,
+                        const int32_t *rowptr, const int32_t *colidx, double *values, int *threads_out)
+{
+    double *Ae = (double *)malloc(sizeof(double) * 144 * (size_t)(n_tets > 0 ? n_tets : 1));
+    int64_t *start = (int64_t *)calloc((size_t)n_nodes + 1, sizeof(int64_t));
+    int64_t *inc = (int64_t *)malloc(sizeof(int64_t) * 4 * (size_t)(n_tets > 0 ? n_tets : 1));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n_nodes + 1));
+    if (!Ae || !start || !inc || !fill) {
+        free(Ae);
+        free(start);
+        free(inc);
+        free(fill);
+        return OR_ENOMEM;
+    }
+    int threads = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        {
+#ifdef _OPENMP
+            threads = omp_get_num_threads();
+#endif
+        }
+#pragma omp for schedule(static)
+        for (int64_t e = 0; e < n_tets; ++e) {
+            if (!mask[e])
+                continue;
+            double X[12];
+            gather_X(x, tets + 4 * e, X);
+            oracle_element(X, E[e], nu, rho, dt, Ae + 144 * e);
+        }
+    }
+    /* node -> (tet, local vertex) lists in ascending tet id (counting sort) */
+    for (int64_t e = 0; e < n_tets; ++e)
+        for (int a = 0; a < 4; ++a)
+            start[tets[4 * e + a] + 1] += 1;
+    for (int64_t i = 0; i < n_nodes; ++i)
+        start[i + 1] += start[i];
+    memcpy(fill, start, sizeof(int64_t) * (size_t)n_nodes);
+    for (int64_t e = 0; e < n_tets; ++e)
+        for (int a = 0; a < 4; ++a)
+            inc[fill[tets[4 * e + a]]++] = 4 * e + a;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n_nodes; ++i)
+        for (int p = 0; p < 3; ++p) {
+            const int64_t row = 3 * i + p;
+            for (int64_t s = rowptr[row]; s < rowptr[row + 1]; ++s) {
+                const int64_t j = colidx[s] / 3, q = colidx[s] % 3;
+                double acc = 0.0;
+                for (int64_t k = start[i]; k < start[i + 1]; ++k) {
+                    const int64_t e = inc[k] / 4;
+                    const int a = (int)(inc[k] % 4);
+                    if (!mask[e])
+                        continue;
+                    for (int b = 0; b < 4; ++b)
+                        if (tets[4 * e + b] == j)
+                            acc = acc + Ae[144 * e + (3 * a + p) * 12 + (3 * b + q)];
+                }
+                values[s] = acc;
+            }
+        }
+    free(Ae);
+    free(start);
+    free(inc);
+    free(fill);
+    if (threads_out)
+        *threads_out = threads;
     return OR_OK;
 }
 
