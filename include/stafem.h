@@ -202,6 +202,22 @@ sta_status sta_set_params(sta_ctx* ctx, const double* x_dev, const double* E_dev
  * Asynchronous on `stream`.  STA_ESTALE after sta_set_params until a rebuild. */
 sta_status sta_adjoint(sta_ctx* ctx, const double* gA_dev, double* g_logE_dev, double* g_x_dev, void* stream);
 
+/* sta_adjoint for callers that cannot allocate device memory (code being
+ * captured into a HIP graph, serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same results, bit for bit, but the per-vertex
+ * cotangent workspace (12 doubles per tet) is a fixed 48 MiB array inside the
+ * library, one per GPU, held until the process ends, instead of a buffer the
+ * context allocates on first use.  Arguments and results as sta_adjoint.
+ * Contexts of more than 524,288 tets are refused with STA_EINVAL (use
+ * sta_adjoint).  The current device must be the context's device.  The
+ * array is shared by every call on one GPU and keeps the last call's
+ * contents (each call overwrites all it reads): calls that may overlap on
+ * one GPU (other streams, other host threads) race and must be serialised
+ * by the caller.  No allocation and no synchronisation; asynchronous on
+ * `stream`.  STA_ESTALE after sta_set_params until a rebuild. */
+sta_status sta_adjoint_noalloc(sta_ctx* ctx, const double* gA_dev, double* g_logE_dev, double* g_x_dev,
+                               void* stream);
+
 /* out_dev[s] = alpha * a_dev[row(s)] * b_dev[col(s)] for every pattern slot s
  * (e.g. the cotangent -lambda u^T of the values behind a linear solve).
  * a_dev, b_dev: device, n_rows; out_dev: device, nnz.  Asynchronous. */

@@ -18,6 +18,9 @@
 // incidence segment in ascending tet id (fixed order, no floating atomics).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <string>
+
 #include "sta_internal.h"
 
 #pragma clang fp contract(off)
@@ -318,3 +321,79 @@ hipError_t launch_slot_outer(int n_rows, const int32_t* rowptr, const int32_t* c
 }
 
 }  // namespace sta
+
+// ---------------------------------------------------------------------------
+// Adjoint without allocation: the per-vertex cotangents live in a fixed
+// device array of the library instead of a context workspace.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// 3 doubles per diagonal incidence (4 per tet): room for 524,288 tets.
+constexpr size_t kNoAllocTets = size_t(1) << 19;
+constexpr size_t kNoAllocDoubles = 12 * kNoAllocTets;  // 48 MiB
+
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch`, looked up once per
+// device (the current one); NULL on failure.
+double* scratch_for_current_device(hipError_t& err)
+{
+    int dev = -1;
+    err = hipGetDevice(&dev);
+    if (err != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        if (err == hipSuccess)
+            err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (err != hipSuccess)
+            return nullptr;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" sta_status sta_adjoint_noalloc(sta_ctx* ctx, const double* gA_dev, double* g_logE_dev, double* g_x_dev,
+                                          void* stream)
+{
+    if (!ctx || (ctx->nnz > 0 && !gA_dev) || (ctx->n_tets > 0 && !g_logE_dev) || (ctx->n_nodes > 0 && !g_x_dev))
+        return STA_EINVAL;
+    if ((size_t)ctx->n_tets > kNoAllocTets) {
+        ctx->errmsg = "sta_adjoint_noalloc: " + std::to_string(ctx->n_tets) + " tets exceed the fixed workspace (" +
+                      std::to_string(kNoAllocTets) + " tets); use sta_adjoint";
+        return STA_EINVAL;
+    }
+    if (ctx->stale) {
+        ctx->errmsg = "parameters changed: call sta_full_rebuild before sta_adjoint_noalloc";
+        return STA_ESTALE;
+    }
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess && dev != ctx->device) {
+        ctx->errmsg = "sta_adjoint_noalloc: the current device is not the context's device";
+        return STA_EINVAL;
+    }
+    double* xbar = e == hipSuccess ? scratch_for_current_device(e) : nullptr;
+    if (!xbar) {
+        ctx->errmsg = std::string("sta_adjoint_noalloc: workspace address: ") + hipGetErrorString(e);
+        return STA_EHIP;
+    }
+    // every diagonal incidence's three entries are written by the element pass
+    // before the node pass reads them, so nothing needs clearing
+    e = sta::launch_adjoint(ctx->v, gA_dev, g_logE_dev, g_x_dev, xbar, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        ctx->errmsg = std::string("sta_adjoint_noalloc launch: ") + hipGetErrorString(e);
+        return STA_EHIP;
+    }
+    return STA_OK;
+}

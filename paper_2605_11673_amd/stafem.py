@@ -56,6 +56,7 @@ SIGNATURES = {
     "sta_kernel_times": (_int, [_vp, _vp, _i64p, ctypes.POINTER(_dbl)]),
     "sta_set_params": (_int, [_vp, _vp, _vp, _vp]),
     "sta_adjoint": (_int, [_vp, _vp, _vp, _vp, _vp]),
+    "sta_adjoint_noalloc": (_int, [_vp, _vp, _vp, _vp, _vp]),
     "sta_slot_outer": (_int, [_vp, _vp, _vp, _dbl, _vp, _vp]),
     "sta_cg_solve": (_int, [_vp, _vp, _vp, _vp, _dbl, _int, _vp, ctypes.POINTER(_int), ctypes.POINTER(_dbl)]),
     "sta_lumped_mass": (_int, [_vp, _vp, _vp]),
