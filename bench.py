@@ -12,13 +12,19 @@ mapping and frame mode are chosen by the library's autotuner on the peak
 frame before timing.  The timed region replays the whole step captured as
 one HIP graph.
 
-Printed (one JSON line): touched slots/s over the timed steps, per-frame
-streaming latency and rebuild time, the HBM roofline of the dominant kernel
-(and of the rebuild kernels), the oracle's CPU rebuild rate on a bounded
-sample, parity (streaming bitwise equal to the GPU rebuild at every frame,
-checked outside the timed region), and the same measurements for the
-refinement/merge stream on the 432,000-tet red-refinement superset and for
-the 64-mesh batch.
+Printed: one compact JSON line on stdout (the last line, a few KB): touched
+slots/s over the timed steps, per-frame streaming and rebuild times (both
+pipelined from HIP graphs and per-frame latency between events), their
+ratios, the HBM roofline of the dominant streaming kernel from the
+method's algorithmic bytes (the design's own byte count and the committed
+counter traffic beside it), the oracle's CPU rebuild rate on a bounded
+sample (one thread, and all host threads), parity (streaming bitwise equal
+to the GPU rebuild at every frame, checked outside the timed region) and a
+one-line summary per secondary workload.  Everything else (the per-frame
+rows, the autotuner's report, every secondary section in full: refinement
+superset, 64-mesh batch in both frame modes, +/- delta policy, proxy
+operator, implicit Euler, connectivity, differentiation) goes to the file
+named by --detail, with a one-line summary of each on stderr.
 """
 from __future__ import annotations
 
@@ -45,7 +51,33 @@ def log(*a):
 
 
 # ---------------------------------------------------------------------------
-# Algorithmic byte models (bytes the kernel must move in this design)
+# Algorithmic bytes of the method (what any exact streaming update must move)
+# ---------------------------------------------------------------------------
+
+def alg_edits(st):
+    """Edit phase: per edit 130 B (the edit, its mask byte read and written, the tet's
+    10 block ids, the block-stamp read-modify-writes); per activation 780 B (vertex ids,
+    coordinates and modulus, 624 B of contributions written)."""
+    return 130 * st["edits"] + 780 * st["activated"]
+
+
+def alg_touched(st):
+    """Re-sum of the touched blocks: per incidence its tet id, mask byte and
+    contribution (48 B diagonal, 72 B off-diagonal); 8 B per slot written (both
+    triangles); 24 B of segment and row metadata per block."""
+    return (53 * st["diag_incidences"] + 77 * st["off_incidences"] + 8 * st["touched_slots"]
+            + 24 * (st["diag_blocks"] + st["off_blocks"]))
+
+
+def alg_frame(st):
+    return alg_edits(st) + alg_touched(st)
+
+
+ALG_MODEL = {"edits": alg_edits, "touched": alg_touched, "frame": alg_frame}
+
+
+# ---------------------------------------------------------------------------
+# Design bytes (what these kernels move as designed, each byte once)
 # ---------------------------------------------------------------------------
 
 def bytes_touched(st):
@@ -158,25 +190,50 @@ def kernel_instance(asm, kernel):
     return kernel
 
 
-def roofline(kernel, alg_bytes, seconds, launches, traffic_key=None, with_traffic=True):
-    """with_traffic: attach the committed counter traffic (taken on the headline workload only)."""
+def roofline(kernel, alg_bytes, seconds, launches, traffic_key=None, with_traffic=True, design_bytes=None):
+    """alg_bytes: the method's algorithmic bytes over all launches; design_bytes (optional):
+    the design's own byte count over the same launches, reported beside it.  with_traffic:
+    attach the committed counter traffic (taken on the headline workload only)."""
     achieved = alg_bytes / seconds / 1e9 if seconds > 0 else 0.0
     tr = load_traffic(traffic_key or kernel) if with_traffic else None
-    return {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": None if tr is None else tr.get("bytes_per_launch"),
-            "algorithmic_bytes_per_launch": round(alg_bytes / max(launches, 1), 1),
-            "avg_launch_us": round(seconds / max(launches, 1) * 1e6, 3), "launches": launches}
+    out = {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+           "traffic": None if tr is None else tr.get("bytes_per_launch"),
+           "algorithmic_bytes_per_launch": round(alg_bytes / max(launches, 1), 1),
+           "avg_launch_us": round(seconds / max(launches, 1) * 1e6, 3), "launches": launches}
+    if design_bytes is not None:
+        out["design_bytes_per_launch"] = round(design_bytes / max(launches, 1), 1)
+    return out
 
 
-def cpu_model():
+def host_info():
+    """The host the CPU baseline ran on: logical CPUs, those this process may use, the
+    OpenMP thread setting and the CPU model as lscpu reports it."""
+    import subprocess
+
+    model = "unknown"
     try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
-    except OSError:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.strip().startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
         pass
-    return "unknown"
+    if model == "unknown":
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
+            "cpu_model": model}
 
 
 # ---------------------------------------------------------------------------
@@ -225,24 +282,26 @@ class Stream:
         self.stats = stats
         return stats, mismatches
 
-    def timed(self, steps, warmup):
+    def timed(self, steps, warmup, kernel_events=True):
         """Kernel durations (events), host-launched step time, graph-replayed step time."""
         torch, asm = self.torch, self.asm
         for _ in range(warmup):
             self.step()
         torch.cuda.synchronize()
-        asm.enable_kernel_timing(True)
-        asm.kernel_times()
-        for _ in range(steps):
-            self.step()
-        ktimes = asm.kernel_times()
-        asm.enable_kernel_timing(False)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            self.step()
-        torch.cuda.synchronize()
-        eager_s = (time.perf_counter() - t0) / steps
+        ktimes, eager_s = {}, 0.0
+        if kernel_events:
+            asm.enable_kernel_timing(True)
+            asm.kernel_times()
+            for _ in range(steps):
+                self.step()
+            ktimes = asm.kernel_times()
+            asm.enable_kernel_timing(False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                self.step()
+            torch.cuda.synchronize()
+            eager_s = (time.perf_counter() - t0) / steps
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
             self.step()
@@ -259,15 +318,37 @@ class Stream:
         return ktimes, eager_s, step_s
 
     def stream_roofline(self, ktimes, steps):
-        per_step = {"touched": sum(bytes_touched(s) for s in self.stats),
-                    "edits": sum(bytes_edits(s) for s in self.stats),
-                    "frame": sum(bytes_frame(s) for s in self.stats)}
+        """Roofline of the dominant streaming kernel (largest summed duration): the method's
+        algorithmic bytes over its launches, the design's bytes beside them."""
+        design = {"touched": bytes_touched, "edits": bytes_edits, "frame": bytes_frame}
         kern = {k: {"launches": n, "avg_us": round(ms * 1e3 / max(n, 1), 3), "total_ms": round(ms, 3)}
                 for k, (n, ms) in ktimes.items()}
         cands = [k for k in ("frame", "touched", "edits") if k in ktimes]
         dom = max(cands, key=lambda k: ktimes[k][1])
-        return kern, roofline("k_" + dom, steps * per_step[dom], ktimes[dom][1] * 1e-3, ktimes[dom][0],
-                              traffic_key=kernel_instance(self.asm, "k_" + dom), with_traffic=self.headline)
+        alg = steps * sum(ALG_MODEL[dom](st) for st in self.stats)
+        des = steps * sum(design[dom](st) for st in self.stats)
+        return kern, roofline("k_" + dom, alg, ktimes[dom][1] * 1e-3, ktimes[dom][0],
+                              traffic_key=kernel_instance(self.asm, "k_" + dom), with_traffic=self.headline,
+                              design_bytes=des)
+
+    def rebuild_pipelined(self, reps=20):
+        """Microseconds per full rebuild with `reps` rebuilds captured as one HIP graph and
+        replayed (timed as the streaming step is), at the current mask."""
+        torch, asm = self.torch, self.asm
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(reps):
+                asm.full_rebuild()
+        g.replay()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(5):
+            g.replay()
+        ev[1].record()
+        ev[1].synchronize()
+        del g
+        return ev[0].elapsed_time(ev[1]) * 1e3 / (5 * reps)
 
     def rebuild_roofline(self, reps=5):
         """Rebuild kernels timed with events at every frame's mask (the step returns to the start)."""
@@ -338,7 +419,7 @@ class Stream:
             nreb = max(4, reps // 2)
             reb = [timed(asm.full_rebuild, False) for _ in range(nreb)]
             reb_cold = [timed(asm.full_rebuild, True) for _ in range(nreb // 2)]
-            alg = bytes_frame(st)
+            alg = alg_frame(st)
             rows.append({"frame": k, "edits": st["edits"], "touched_blocks": st["touched_blocks"],
                          "touched_slots": st["touched_slots"], "stream_us": round(float(np.median(warm)), 3),
                          "stream_cold_us": round(float(np.median(cold)), 3) if cold else None,
@@ -388,19 +469,35 @@ def cpu_baseline(args, w, frames, stats):
         masks.append(mask.copy())
     idx = np.linspace(0, len(frames) - 1, num=min(args.cpu_sample, len(frames))).round().astype(int)
     t_total, slots = 0.0, 0
+    serial = {}
     for k in idx:
         t0 = time.perf_counter()
-        oracle.rebuild(w.x, w.tets, w.E, w.nu, w.rho, w.dt, masks[k], *pat)
+        serial[int(k)] = oracle.rebuild(w.x, w.tets, w.E, w.nu, w.rho, w.dt, masks[k], *pat)
         t_total += time.perf_counter() - t0
         slots += stats[k]["touched_slots"]
+    # the same rebuilds row by row on every host thread, checked bitwise against the serial ones
+    t_par, slots_par, threads, same = 0.0, 0, 0, True
+    for k in idx:
+        t0 = time.perf_counter()
+        v, threads = oracle.rebuild_rows(w.x, w.tets, w.E, w.nu, w.rho, w.dt, masks[k], *pat)
+        t_par += time.perf_counter() - t0
+        slots_par += stats[k]["touched_slots"]
+        same = same and bool(np.array_equal(v.view(np.uint64), serial[int(k)].view(np.uint64)))
+    info = host_info()
     return {"value": slots / t_total, "unit": "touched slots/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle full rebuild from the mask at {len(idx)} of the {len(frames)} frames of one step "
                       f"(frames {idx.tolist()}), single-threaded, {t_total:.1f} s",
-            "rebuild_s_per_frame": round(t_total / len(idx), 4), "host_cpu": cpu_model()}
+            "rebuild_s_per_frame": round(t_total / len(idx), 4), **info,
+            "multicore": {"value": slots_par / t_par, "unit": "touched slots/s", "cores": threads,
+                          "rebuild_s_per_frame": round(t_par / len(idx), 4),
+                          "bitwise_equal_to_serial": same,
+                          "sample": "the same frames, row-parallel oracle rebuild on every host thread"}}
 
 
-def secondary(torch, name, asm, frames, n_tets, n_nodes, mask0, peak, args, describe):
-    """Tuned, parity-checked, graph-timed stream of another workload."""
+def secondary(torch, name, asm, frames, n_tets, n_nodes, mask0, peak, args, describe, fused_too=False):
+    """Tuned, parity-checked, graph-timed stream of another workload; with fused_too the
+    same stream also in the one-launch frame mode (the tuned slot mapping, its own parity
+    check and timing)."""
     log(f"[bench] {name}: {n_tets} tets, {len(frames)} frames")
     s = Stream(torch, asm, frames, n_tets, n_nodes, mask0, headline=False)
     cfg, _ = s.tune(peak)
@@ -421,6 +518,28 @@ def secondary(torch, name, asm, frames, n_tets, n_nodes, mask0, peak, args, desc
            "kernels": kern, "parity": {"frames_checked": len(frames), "mismatching_frames": mism}}
     log(f"[bench] {name}: {step_s * 1e3:.3f} ms/step, {frame_us:.2f} us/frame, "
         f"rebuild {reb['rebuild_us_mean']} us, parity mismatches {mism}")
+    if fused_too:
+        # the grid cap of the persistent launch: the fastest of a few, timed on the step
+        best = None
+        for cap in (32, 64, 128, 256):
+            apply_config(asm, dict(cfg, fused=1, grid_cap=cap))
+            _, _, t = s.timed(1, 1, kernel_events=False)
+            if best is None or t < best[1]:
+                best = (cap, t)
+        fcfg = dict(cfg, fused=1, grid_cap=best[0])
+        apply_config(asm, fcfg)
+        _, fmism = s.stats_pass(check_parity=True)
+        fkt, _, fstep_s = s.timed(steps, 1)
+        fkern, froof = s.stream_roofline(fkt, steps)
+        ffus = fstep_s * 1e6 / len(frames)
+        out["one_launch"] = {"config": {k: v for k, v in fcfg.items() if k != "buckets"},
+                             "stream_pipelined_us_per_frame": round(ffus, 3), "value": slots / fstep_s,
+                             "rebuild_vs_pipelined_frame": round(reb["rebuild_us_mean"] / ffus, 2),
+                             "roofline": froof, "kernels": fkern,
+                             "parity": {"frames_checked": len(frames), "mismatching_frames": fmism}}
+        assert asm.status_sync() == 0, "one-launch frame reported a device error"
+        apply_config(asm, cfg)
+        log(f"[bench] {name}, one launch per frame: {ffus:.2f} us/frame, parity mismatches {fmism}")
     return out
 
 
@@ -812,6 +931,11 @@ def gradient_section(torch, stafem, workloads, args, rtol=1e-10, reps=5):
     return out
 
 
+# Connectivity is rebuilt from the mask periodically (paper Sec. 3.6), with no period given:
+# here once per 4 frames, the frames per scenario of the paper's elasticity study (Sec. 5).
+CONNECTIVITY_PERIOD = 4
+
+
 def connectivity_section(torch, stafem, w, frames, args):
     """Connectivity rebuilt from the mask after every frame of the headline stream, for
     both adjacencies (union-find over the active tets' vertices; over the candidate face
@@ -845,8 +969,10 @@ def connectivity_section(torch, stafem, w, frames, args):
             r["counts"].append(k)
     n_pairs = 0  # candidate face pairs, counted in the CPU-baseline leg
     asm.close()
+    period = CONNECTIVITY_PERIOD
     out = {"workload": "components of the active tets rebuilt after every frame of the headline stream, "
-                       "shared-vertex and shared-face adjacency"}
+                       "shared-vertex and shared-face adjacency; cost per frame when rebuilt every "
+                       f"{period} frames", "period_frames": period}
     oracle_s = {}
     if not args.no_cpu_baseline:
         # the oracle's components at the peak frame's mask (library connected_components)
@@ -868,7 +994,8 @@ def connectivity_section(torch, stafem, w, frames, args):
         out[adj] = {"rebuild_us_median": round(med, 3),
                     "rebuild_us_max": round(float(np.max(r["times"])), 3),
                     "components_initial": c[0], "components_max": int(max(c)), "components_final": c[-1],
-                    "repeat_labels_identical": r["stable"]}
+                    "repeat_labels_identical": r["stable"],
+                    "us_per_frame_at_period": round(med / period, 3)}
         if adj == "vertex" or n_pairs:
             nb = bytes_connectivity_pass(w.n_tets, w.n_nodes, n_pairs if adj == "face" else 0)
             out[adj]["roofline"] = roofline(f"connectivity ({adj}), one-pass lower bound", nb, med * 1e-6, 1,
@@ -884,6 +1011,78 @@ def connectivity_section(torch, stafem, w, frames, args):
     return out
 
 
+def compact_line(out, detail_path):
+    """The default line: the headline numbers and a short summary of each section (the
+    full report is in the detail file)."""
+    pf = out.get("per_frame", {})
+    line = {k: out[k] for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                                "higher_is_better", "scaling", "vs_baseline", "dtype", "data")}
+    line["config"] = {k: out["config"][k] for k in ("workload", "n_tets", "nnz", "frames_per_step",
+                                                    "edits_per_step", "touched_slots_per_step", "seed")}
+    line["config"]["frame_mode"] = "one launch" if out["tuned_config"]["fused"] else "two launches"
+    line["timing_mode"] = out["timing_mode"]
+    if pf:
+        line["per_frame_us"] = pf["us"]
+        line["stream_vs_rebuild"] = pf["ratios"]
+    line["roofline"] = out["roofline"]
+    if "frame_roofline" in out:
+        line["frame_roofline"] = out["frame_roofline"]
+    if "roofline_rebuild" in out:
+        rr = out["roofline_rebuild"]
+        line["roofline_rebuild"] = {"element_frac": rr["element"]["frac"], "reduce_frac": rr["reduce"]["frac"],
+                                    "whole_frac": rr["whole_frac"], "kernel_us": rr["rebuild_us_mean"]}
+    if "hbm_measured" in out:
+        line["hbm_measured_GBs"] = out["hbm_measured"]
+    if "cpu_baseline" in out:
+        cb = dict(out["cpu_baseline"])
+        cb["sample"] = cb["sample"].split(" (frames")[0]
+        cb["multicore"] = {k: v for k, v in cb["multicore"].items() if k != "sample"}
+        line["cpu_baseline"] = cb
+    line["parity"] = out["parity"]
+    sec = {}
+    for name in ("refinement", "batch"):
+        if name in out:
+            o = out[name]
+            sec[name] = {"us_per_frame": o["stream_pipelined_us_per_frame"], "rebuild_us": o["rebuild_us_mean"],
+                         "ratio": o["rebuild_vs_pipelined_frame"], "frac": o["roofline"]["frac"],
+                         "mismatching_frames": o["parity"]["mismatching_frames"]}
+            if "one_launch" in o:
+                ol = o["one_launch"]
+                sec[name]["one_launch_us_per_frame"] = ol["stream_pipelined_us_per_frame"]
+                sec[name]["one_launch_mismatching_frames"] = ol["parity"]["mismatching_frames"]
+    if "delta" in out:
+        d = out["delta"]
+        sec["delta"] = {"us_per_frame": d["delta_us_per_frame"], "exact_us_per_frame": d["exact_us_per_frame"],
+                        "drift_max_abs": d["drift"]["max_abs"]}
+    if "proxy" in out:
+        p = out["proxy"]
+        sec["proxy"] = {"us_per_frame": p["stream_pipelined_us_per_frame"], "rebuild_us": p["rebuild_us_median"],
+                        "mismatching_frames": p["parity"]["mismatching_frames"]}
+    if "euler" in out:
+        e = out["euler"]
+        sec["euler"] = {"frame_us_stream": e["policies"]["stream"]["frame_us_mean"],
+                        "frame_us_rebuild": e["policies"]["rebuild"]["frame_us_mean"],
+                        "cg_frac": e["roofline"]["frac"], "bitwise_same_trajectory": e["trajectories_bitwise_equal"]}
+    if "gradient" in out:
+        g = out["gradient"]
+        sec["gradient"] = {"cg_us_per_iteration": g["cg"]["us_per_iteration"], "cg_frac": g["cg"]["roofline"]["frac"],
+                           "adjoint_us": g["adjoint"]["us"], "adjoint_frac": g["adjoint"]["roofline"]["frac"]}
+    if "connectivity" in out:
+        c = out["connectivity"]
+        sec["connectivity"] = {a: {"rebuild_us": c[a]["rebuild_us_median"],
+                                   "us_per_frame_at_period": c[a]["us_per_frame_at_period"]}
+                               for a in ("vertex", "face")}
+        sec["connectivity"]["period_frames"] = c["period_frames"]
+    if sec:
+        line["sections"] = sec
+    line["detail"] = detail_path
+    text = json.dumps(line)
+    if len(text) > 4000:  # keep the line short: the sections are in the detail file
+        line.pop("sections", None)
+        text = json.dumps(line)
+    return text
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -893,13 +1092,15 @@ def main():
                     help="repetitions per frame for the per-frame breakdown (half warm, half after a cache flush)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the refinement and batch workloads")
+    ap.add_argument("--no-extras", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--no-tune", action="store_true", help="keep the default configuration")
     ap.add_argument("--config", default=None,
                     help="force fused,rebuild_qd,rebuild_qo,stream_qd,stream_qo,grid_cap,rebuild_nt (skips tuning)")
     ap.add_argument("--cpu-sample", type=int, default=48, help="oracle rebuilds in the CPU baseline sample")
     ap.add_argument("--quick", action="store_true",
                     help="headline timed steps, 3 rebuilds and a 256 MiB reference copy only (for profiler runs)")
+    ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file for the full report (per-frame rows, autotuner report, every section)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -932,6 +1133,8 @@ def main():
     value = slots_per_step / step_s
     log(f"[bench] graph {step_s * 1e3:.3f} ms/step ({value:.4g} slots/s), host-launched {eager_s * 1e3:.3f} ms/step")
     kern, roof = s.stream_roofline(ktimes, args.steps)
+    frame_us = step_s * 1e6 / len(frames)
+    alg_step = sum(alg_frame(st) for st in stats)
 
     out = {
         "metric": METRIC, "value": value, "unit": "touched slots/s", "n_gpus": 1, "steps": args.steps,
@@ -945,8 +1148,13 @@ def main():
                          "buckets": {k: asm.bucket_map(k) for k in ("rebuild", "stream")}},
         "timing_mode": "whole step captured as one HIP graph, replayed",
         "host_launched": {"ms_per_step": eager_s * 1e3, "value": slots_per_step / eager_s},
-        "stream_pipelined_us_per_frame": round(step_s * 1e6 / len(frames), 3),
+        "stream_pipelined_us_per_frame": round(frame_us, 3),
         "roofline": roof,
+        # both streaming kernels as one unit: the method's bytes per frame over the pipelined frame time
+        "frame_roofline": {"kernels": "k_edits+k_touched per frame (pipelined)", "bound": "hbm",
+                           "achieved": round(alg_step / step_s / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(alg_step / step_s / 1e9 / HBM_PEAK_GBS, 5),
+                           "algorithmic_bytes_per_frame": round(alg_step / len(frames), 1)},
         "kernels": kern,
         "parity": {"frames_checked": 0 if args.quick else len(frames), "mismatching_frames": mismatches,
                    "check": "GPU streaming values bitwise equal to GPU full rebuild at every frame"},
@@ -964,14 +1172,37 @@ def main():
     if not args.quick:
         out["latency_floor"] = stafem.latency_probe()
         out["hbm_measured"] = {k: round(x, 1) for k, x in stafem.bandwidth_probe().items()}
-        out["roofline_rebuild"] = s.rebuild_roofline()
-        out.update(s.per_frame(args.reps))
-        out["stream_vs_rebuild"]["pipelined_ratio"] = round(
-            out["rebuild_us"]["median"] / out["stream_pipelined_us_per_frame"], 2)
+        rr = s.rebuild_roofline()
+        rb = rr["element"]["algorithmic_bytes_per_launch"] + rr["reduce"]["algorithmic_bytes_per_launch"]
+        rr["whole_frac"] = round(rb / (rr["rebuild_us_mean"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 5)
+        out["roofline_rebuild"] = rr
+        reb_pipe = s.rebuild_pipelined()
+        pfr = s.per_frame(args.reps)
+        out["per_frame_detail"] = pfr
+        out["per_frame"] = {
+            "us": {"stream_pipelined": round(frame_us, 3), "rebuild_pipelined": round(reb_pipe, 3),
+                   "stream_warm_median": pfr["stream_us_per_frame"]["median"],
+                   "rebuild_warm_median": pfr["rebuild_us"]["median"],
+                   "stream_cold_median": (pfr["stream_cold_us_per_frame"] or {}).get("median"),
+                   "rebuild_cold_median": pfr["rebuild_cold_us"]["median"],
+                   "stream_warm_max": pfr["stream_us_per_frame"]["max"]},
+            "ratios": {"pipelined": round(reb_pipe / frame_us, 2),
+                       "warm_median": pfr["stream_vs_rebuild"]["median_ratio"],
+                       "cold_median": round(pfr["rebuild_cold_us"]["median"]
+                                            / (pfr["stream_cold_us_per_frame"] or {"median": np.nan})["median"], 2),
+                       "peak_frame_warm": pfr["stream_vs_rebuild"]["peak_frame_ratio"],
+                       "target": 20.0}}
         out["autotune_report"] = tune_report
+        log(f"[bench] per frame: stream {frame_us:.2f} us pipelined / {pfr['stream_us_per_frame']['median']} us "
+            f"warm median; rebuild {reb_pipe:.1f} us pipelined / {pfr['rebuild_us']['median']} us warm median; "
+            f"ratios {out['per_frame']['ratios']}")
     asm.close()
     if not args.quick and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, w, frames, stats)
+        cb = out["cpu_baseline"]
+        log(f"[bench] cpu baseline: {cb['rebuild_s_per_frame']} s per oracle rebuild (1 thread), "
+            f"{cb['multicore']['rebuild_s_per_frame']} s on {cb['multicore']['cores']} threads "
+            f"(bitwise equal: {cb['multicore']['bitwise_equal_to_serial']}); {cb['cpu_model']}, nproc {cb['nproc']}")
     if not args.quick and not args.no_extras:
         out["delta"] = delta_section(torch, stafem, w, frames, out["tuned_config"], step_s, args, stats,
                                      out.get("cpu_baseline", {}).get("rebuild_s_per_frame"))
@@ -1003,9 +1234,15 @@ def main():
         out["batch"] = secondary(torch, "batch of 64 meshes", b, bframes, b.n_tets, b.n_nodes, mask0, 12, args,
                                  f"64 jittered Kuhn cubes of 6n^3 tets (n log-uniform, {b.n_tets} tets in all), "
                                  "each with its own 24-frame fracture stream, then reinsertion; one context, "
-                                 "one frame = all meshes' edits, FP64")
+                                 "one frame = all meshes' edits, FP64", fused_too=True)
         b.close()
-    print(json.dumps(out), flush=True)
+    if args.detail:
+        d = os.path.dirname(args.detail)
+        if d:
+            os.makedirs(d, exist_ok=True)
+        with open(args.detail, "w") as f:
+            json.dump(out, f, indent=1)
+    print(compact_line(out, args.detail), flush=True)
 
 
 if __name__ == "__main__":

@@ -73,7 +73,8 @@ typedef int sta_status;
 #define STA_ERANGE (-6)       /* an edit id is outside [0, n_tets) or a state is not 0/1 */
 #define STA_EDUP (-7)         /* an edit list names the same tet twice */
 #define STA_ETIMEOUT (-8)     /* a fused frame could not synchronise its grid (GPU shared with
-                                 other work); the frame is incomplete: call sta_full_rebuild */
+                                 other work); the frame is incomplete (the mask holds its edits)
+                                 and frames are refused (STA_ESTALE) until sta_full_rebuild */
 
 /* Build the superset pattern and the initial matrix (Sec. 3.1 inputs:
  * vertices, candidate pool, initial mask; Alg. 1 initialisation).
@@ -93,7 +94,9 @@ sta_status sta_build_pattern(const double* x, int64_t n_nodes, const int32_t* te
 
 /* Policy full_rebuild (Sec. 3.5): recompute the element matrices of every
  * active tet and re-sum every entry of A from the current mask.  Clears
- * STA_ESTALE.  Asynchronous on `stream`. */
+ * STA_ESTALE.  After fused frames (sta_set_config fused = 1) it also releases
+ * every edit stamp, which a frame whose grid barrier gave up may have left
+ * taken.  Asynchronous on `stream`. */
 sta_status sta_full_rebuild(sta_ctx* ctx, void* stream);
 
 /* Streaming update for one frame (Sec. 3.2, Alg. 1): edit k sets tet
@@ -294,6 +297,14 @@ sta_status sta_set_config(sta_ctx* ctx, int fused, int rebuild_qd, int rebuild_q
                           int grid_cap, int rebuild_nt);
 sta_status sta_get_config(const sta_ctx* ctx, int* out7);
 
+/* Failure injection for the fused frame (tests of STA_ETIMEOUT): the grid
+ * barrier between the two phases gives up after `polls` polls of its
+ * release word (0 restores the default, 2^24, far beyond any co-resident
+ * grid's wait).  A small value makes workgroups that arrive early give up
+ * and leave; the device records STA_ETIMEOUT for sta_status_sync.
+ * STA_EINVAL for polls < 0 or >= 2^32. */
+sta_status sta_set_barrier_spin_limit(sta_ctx* ctx, int64_t polls);
+
 /* Slot mapping per incidence-length bucket.  A block's incidence length
  * kappa is the number of candidate tets in its segment (paper Sec. 3.3:
  * the per-block work of a local recompute, O(|Delta| kappa) in Prop. 1).
@@ -365,7 +376,10 @@ sta_status sta_latency_probe(void* stream, double* out4);
 sta_status sta_bandwidth_probe(void* stream, double* out3);
 
 /* Synchronise `stream`, return and clear the first error the device
- * recorded (STA_ERANGE, STA_EDUP, STA_EDEGENERATE), else STA_OK. */
+ * recorded (STA_ETIMEOUT, STA_ERANGE, STA_EDUP, STA_EDEGENERATE), else
+ * STA_OK.  On STA_ETIMEOUT it also releases every edit stamp and marks the
+ * context stale, so that sta_apply_edits returns STA_ESTALE until
+ * sta_full_rebuild re-sums the matrix from the mask. */
 sta_status sta_status_sync(sta_ctx* ctx, void* stream);
 
 /* Message for the last error on this context (or of the last failed

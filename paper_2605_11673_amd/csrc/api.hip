@@ -372,7 +372,11 @@ sta_status run_frame(sta_ctx* ctx, const int32_t* ids, const uint8_t* states, in
         const int grid = frame_grid_for(ctx->stream_map, n_host, ctx->frame_max_grid, ctx->frame_grid_cap);
         e = timed(
             ctx, STA_KERNEL_FRAME, s,
-            [&] { return launch_frame(ctx->v, ctx->stream_map, grid, ids, states, n_host, n_dev, s); }, true);
+            [&] {
+                return launch_frame(ctx->v, ctx->stream_map, grid, ids, states, n_host, n_dev, ctx->barrier_spin, s);
+            },
+            true);
+        ctx->fused_used = true;
     } else {
         e = timed(
             ctx, STA_KERNEL_EDITS, s, [&] { return launch_edit_phase(ctx->v, ids, states, n_host, n_dev, s); },
@@ -409,8 +413,16 @@ sta_status sta_full_rebuild(sta_ctx* ctx, void* stream)
     if (!ctx)
         return STA_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = timed(
-        ctx, STA_KERNEL_ELEMENT, s, [&] { return launch_element(ctx->v, ctx->rebuild_map.nt != 0, s); }, true);
+    hipError_t e = hipSuccess;
+    if (ctx->fused_used) {
+        // a fused frame whose grid barrier gave up leaves stamps taken: release them all
+        e = launch_clear_stamps(ctx->v, s);
+        if (e == hipSuccess)
+            ctx->fused_used = ctx->fused != 0;
+    }
+    if (e == hipSuccess)
+        e = timed(
+            ctx, STA_KERNEL_ELEMENT, s, [&] { return launch_element(ctx->v, ctx->rebuild_map.nt != 0, s); }, true);
     if (e == hipSuccess)
         e = timed(
             ctx, STA_KERNEL_REDUCE, s, [&] { return launch_reduce_all(ctx->v, ctx->rebuild_map, s); }, true);
@@ -639,10 +651,20 @@ sta_status sta_status_sync(sta_ctx* ctx, void* stream)
     if (e != hipSuccess)
         return hip_fail(ctx, e, "status sync");
     if (bits & ERR_TIMEOUT) {
+        // Workgroups that gave up left before phase 2: their share of the touched
+        // blocks was not re-summed and the stamps it would have released stay
+        // taken.  Release every stamp now and refuse frames until a rebuild.
         const uint32_t zero2[2] = {0u, 0u};
-        (void)hipMemcpy(&ctx->v.ctl->bar_count, zero2, sizeof(zero2), hipMemcpyHostToDevice);
-        ctx->errmsg = "a fused frame's grid barrier timed out (GPU shared with other work); "
-                      "the frame is incomplete, call sta_full_rebuild";
+        e = hipMemcpy(&ctx->v.ctl->bar_count, zero2, sizeof(zero2), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = launch_clear_stamps(ctx->v, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        ctx->stale = true;
+        if (e != hipSuccess)
+            return hip_fail(ctx, e, "status sync after a barrier timeout");
+        ctx->errmsg = "a fused frame's grid barrier timed out (GPU shared with other work); the frame is "
+                      "incomplete (the mask holds its edits): call sta_full_rebuild before the next frame";
         return STA_ETIMEOUT;
     }
     const sta_status st = device_errors(bits);
@@ -681,6 +703,14 @@ sta_status sta_get_config(const sta_ctx* ctx, int* out7)
     out6[4] = ctx->stream_map.qo;
     out6[5] = ctx->frame_grid_cap;
     out6[6] = ctx->rebuild_map.nt;
+    return STA_OK;
+}
+
+sta_status sta_set_barrier_spin_limit(sta_ctx* ctx, int64_t polls)
+{
+    if (!ctx || polls < 0 || polls > (int64_t)UINT32_MAX)
+        return STA_EINVAL;
+    ctx->barrier_spin = polls == 0 ? kBarrierSpinDefault : (unsigned)polls;
     return STA_OK;
 }
 

@@ -243,6 +243,11 @@ __device__ __forceinline__ void zero_element(const DevView& v, const int* pos)
 // lane that holds it.  The additions are the same whatever Q is, so the
 // result is bit-identical across mappings.  src0: wave lane of the group's
 // lane 0; groups of Q lanes never straddle a wave.
+//
+// Padding terms past the segment end load the segment's last term (always
+// in range, and on a line the group loads anyway) and are then replaced by
+// +0.0: the CH loads issue back to back with no branch around each, where a
+// guarded load per term cost an exec-mask branch apiece.
 template <int Q, int CH, bool NT = false>
 __device__ __forceinline__ double seg_sum(const double* __restrict__ c, int stride, int vi, int k0, int k1, int q,
                                           int src0)
@@ -253,8 +258,12 @@ __device__ __forceinline__ double seg_sum(const double* __restrict__ c, int stri
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             const int k = base + q + j * Q;
-            t[j] = k < k1 ? ld<NT>(c + (size_t)k * stride + vi) : 0.0;
+            const int kc = k < k1 ? k : k1 - 1;  // base < k1, so kc is in [k0, k1)
+            t[j] = ld<NT>(c + (size_t)kc * stride + vi);
         }
+#pragma unroll
+        for (int j = 0; j < CH; ++j)
+            t[j] = base + q + j * Q < k1 ? t[j] : 0.0;
         if (Q == 1) {
 #pragma unroll
             for (int j = 0; j < CH; ++j)
@@ -1049,11 +1058,11 @@ __global__ __launch_bounds__(kBlock) void k_delta_clear(DevView v, const int32_t
 }
 
 // Grid-wide barrier for a co-resident grid (the host sizes the grid from the
-// occupancy so that every workgroup is resident).  The spin is bounded: a
-// grid that is not co-resident reports ERR_TIMEOUT instead of hanging.
-constexpr unsigned kBarrierSpinLimit = 1u << 24;
+// occupancy so that every workgroup is resident).  The spin is bounded (at
+// most spin_limit polls): a grid that is not co-resident reports ERR_TIMEOUT
+// instead of hanging.
 
-__device__ __forceinline__ bool grid_barrier(Ctl* ctl, unsigned G, int* s_ok)
+__device__ __forceinline__ bool grid_barrier(Ctl* ctl, unsigned G, unsigned spin_limit, int* s_ok)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1069,7 +1078,7 @@ __device__ __forceinline__ bool grid_barrier(Ctl* ctl, unsigned G, int* s_ok)
             unsigned spins = 0;
             while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
                 __builtin_amdgcn_s_sleep(1);
-                if (++spins > kBarrierSpinLimit) {
+                if (++spins >= spin_limit) {
                     ok = 0;
                     atomicOr(&ctl->err, ERR_TIMEOUT);
                     break;
@@ -1089,7 +1098,8 @@ __device__ __forceinline__ bool grid_barrier(Ctl* ctl, unsigned G, int* s_ok)
 template <int QD, int QO, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_frame(DevView v, const int32_t* __restrict__ ids,
                                                   const uint8_t* __restrict__ states, int32_t n_host,
-                                                  const int32_t* __restrict__ n_dev, MapConfig m)
+                                                  const int32_t* __restrict__ n_dev, MapConfig m,
+                                                  unsigned spin_limit)
 {
     __shared__ int s_bits;
     __shared__ int s_ok;
@@ -1111,7 +1121,7 @@ __global__ __launch_bounds__(kBlock) void k_frame(DevView v, const int32_t* __re
     bits = block_or(bits, &s_bits);
     if (threadIdx.x == 0)
         v.wg_err[blockIdx.x] = (uint8_t)bits;
-    if (!grid_barrier(v.ctl, gridDim.x, &s_ok))
+    if (!grid_barrier(v.ctl, gridDim.x, spin_limit, &s_ok))
         return;
     const int fe = frame_error(v, gridDim.x, &s_bits);
     publish_frame(v, fe, n, regions);
@@ -1127,6 +1137,17 @@ __global__ __launch_bounds__(kBlock) void k_frame(DevView v, const int32_t* __re
             touched_edit(v, ids[w], v.undo[w], fe);
         }
     }
+}
+
+// Release every tet and block stamp (after a fused frame whose grid barrier
+// gave up, some workgroups left before phase 2 and their stamps stay taken).
+__global__ __launch_bounds__(kBlock) void k_clear_stamps(DevView v)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < v.n_tets)
+        v.estamp[i] = 0u;
+    if (i < v.nd + v.no)
+        v.bstamp[i] = 0u;
 }
 
 __global__ __launch_bounds__(kBlock) void k_set_params(int n_nodes, int n_tets, const double* __restrict__ x_aos,
@@ -1293,21 +1314,30 @@ int frame_grid_for(const MapConfig& m, int32_t n_host, int max_grid, int grid_ca
 }
 
 hipError_t launch_frame(const DevView& v, const MapConfig& m, int grid, const int32_t* ids, const uint8_t* states,
-                        int32_t n_host, const int32_t* n_dev, hipStream_t s)
+                        int32_t n_host, const int32_t* n_dev, unsigned spin_limit, hipStream_t s)
 {
 #define LAUNCH(QD, QO)                                                                                        \
     if (m.qd == QD && m.qo == QO) {                                                                           \
         if (mixed_map(m))                                                                                     \
             launch_kernel(&k_frame<QD, QO, true>, dim3(grid), dim3(kBlock), 0, s, v, ids, states, n_host,     \
-                          n_dev, m);                                                                          \
+                          n_dev, m, spin_limit);                                                              \
         else                                                                                                  \
             launch_kernel(&k_frame<QD, QO, false>, dim3(grid), dim3(kBlock), 0, s, v, ids, states, n_host,    \
-                          n_dev, m);                                                                          \
+                          n_dev, m, spin_limit);                                                              \
         return hipGetLastError();                                                                             \
     }
     STA_MAPPINGS(LAUNCH)
 #undef LAUNCH
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_clear_stamps(const DevView& v, hipStream_t s)
+{
+    const int64_t n = v.n_tets > v.nd + v.no ? v.n_tets : v.nd + v.no;
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_clear_stamps, dim3(blocks_for(n)), dim3(kBlock), 0, s, v);
+    return hipGetLastError();
 }
 
 hipError_t launch_refresh_records(const DevView& v, TetRecord* trec, hipStream_t s)

@@ -33,6 +33,9 @@ struct Ctl {
     int32_t pad;
 };
 
+// Polls of the fused frame's grid barrier before it reports ERR_TIMEOUT.
+constexpr unsigned kBarrierSpinDefault = 1u << 24;
+
 // Incidence-length buckets of the slot mapping: a block's segment length
 // kappa (its number of candidate tets) puts a diagonal block in bucket 0
 // (kappa <= 8), 1 (9..32) or 2 (> 32), an off-diagonal block in bucket 0
@@ -185,6 +188,8 @@ struct sta_ctx {
     int fused = 0;          // 1: one persistent launch per frame
     int frame_grid_cap = 0; // 0: occupancy limit only
     int frame_max_grid = 0; // co-resident workgroups for the fused kernel (per stream_map)
+    unsigned barrier_spin = sta::kBarrierSpinDefault;  // polls before the fused frame's barrier gives up
+    bool fused_used = false;  // a fused frame ran since the last rebuild (stamps may be left taken)
     // lazily allocated workspaces
     double* cg_ws = nullptr;        // 7 vectors of n_rows (two copies of p) + partials
     int32_t* cg_dpos = nullptr;
@@ -254,7 +259,9 @@ hipError_t launch_delta_frame(const DevView& v, const int32_t* ids, const uint8_
 hipError_t frame_max_grid(const MapConfig& m, int device, int* max_grid);
 int frame_grid_for(const MapConfig& m, int32_t n_host, int max_grid, int grid_cap);
 hipError_t launch_frame(const DevView& v, const MapConfig& m, int grid, const int32_t* ids, const uint8_t* states,
-                        int32_t n_host, const int32_t* n_dev, hipStream_t s);
+                        int32_t n_host, const int32_t* n_dev, unsigned spin_limit, hipStream_t s);
+// Release every tet and block stamp (a fill kernel, so that it can be captured).
+hipError_t launch_clear_stamps(const DevView& v, hipStream_t s);
 hipError_t launch_set_params(const DevView& v, const double* x_aos, const double* E, double* xs, double* ys,
                              double* zs, double* Eout, hipStream_t s);
 // Copy the current coordinates and moduli into the tet records.

@@ -65,6 +65,7 @@ SIGNATURES = {
     "sta_face_components": (_int, [_vp, _vp, _i64p, _vp]),
     "sta_set_config": (_int, [_vp, _int, _int, _int, _int, _int, _int, _int]),
     "sta_get_config": (_int, [_vp, ctypes.POINTER(_int)]),
+    "sta_set_barrier_spin_limit": (_int, [_vp, _i64]),
     "sta_set_bucket_map": (_int, [_vp, _int, _vp, _vp]),
     "sta_get_bucket_map": (_int, [_vp, _int, _vp, _vp, _vp]),
     "sta_autotune": (_int, [_vp, _vp, _vp, _i64, _int, _vp, ctypes.c_char_p, _i64]),
@@ -333,6 +334,11 @@ class Assembler:
         out = (ctypes.c_int * 7)()
         _check(load().sta_get_config(self._ctx, out), self._ctx)
         return dict(zip(self.CONFIG, list(out)))
+
+    def set_barrier_spin_limit(self, polls: int):
+        """Polls before the fused frame's grid barrier gives up (0: the default); a
+        failure-injection aid for tests of STA_ETIMEOUT."""
+        _check(load().sta_set_barrier_spin_limit(self._ctx, int(polls)), self._ctx)
 
     def set_bucket_map(self, which: str, diag, off):
         """Slot mapping per incidence-length bucket (see sta_set_bucket_map): which is

@@ -169,3 +169,40 @@ def test_autotune_and_cache(tmp_path, monkeypatch):
     rep2 = asm2.autotune(di, ds)
     assert rep2.startswith("cached") and asm2.get_config() == cfg
     asm2.close()
+
+
+def test_fused_barrier_timeout_recovers():
+    """The fused frame's grid barrier made to give up from the host (a spin limit of one
+    poll; every kernel still exits normally): the device reports STA_ETIMEOUT, frames are
+    refused until a rebuild, and after sta_full_rebuild every later frame, fused or not,
+    is bitwise equal to the oracle (no edit stamp stays taken)."""
+    Sm = S()
+    w = W.make_fracture(seed=3, n=16, counts=[1500, 1200, 900, 600])
+    frames = list(w.frames) + W.merge_stream(w.frames)
+    pat = oracle.pattern(w.n_nodes, w.tets)
+    asm = Sm.Assembler.from_workload(w)
+    asm.set_config(fused=1)
+    asm.set_barrier_spin_limit(1)
+    print(f"[timeout] tets={w.n_tets} frame 0 with {len(frames[0][0])} edits, spin limit 1", flush=True)
+    asm.apply_edits(*Sm.upload_frame(*frames[0]))
+    code = asm.status_sync()
+    mask = w.mask0.copy()
+    mask[frames[0][0]] = frames[0][1]
+    if code == Sm.STA_ETIMEOUT:
+        with pytest.raises(Sm.StafemError) as ex:
+            asm.apply_edits(*Sm.upload_frame(*frames[1]))
+        assert ex.value.code == Sm.STA_ESTALE
+    else:  # every workgroup arrived within one poll: the frame is complete
+        assert code == Sm.STA_OK
+    asm.set_barrier_spin_limit(0)
+    asm.full_rebuild()
+    check(host_values(asm), oracle.rebuild_workload(w, mask, pat), "rebuild after the timeout")
+    for t, (ids, st) in enumerate(frames[1:], 1):
+        if t == 4:
+            asm.set_config(fused=0)
+        asm.apply_edits(*Sm.upload_frame(ids, st))
+        mask[ids] = st
+        check(host_values(asm), oracle.rebuild_workload(w, mask, pat), f"frame {t} after the timeout")
+    assert asm.status_sync() == Sm.STA_OK
+    asm.close()
+    assert code == Sm.STA_ETIMEOUT, "the one-poll barrier did not give up (recovery checked anyway)"
