@@ -105,7 +105,10 @@ __device__ __forceinline__ void gather_block(const DevView& v, const double* __r
 __global__ __launch_bounds__(kBlock) void k_adjoint_element(DevView v, const double* __restrict__ gA,
                                                             double* __restrict__ g_logE, double* __restrict__ xbar)
 {
-    const int e = blockIdx.x * kBlock + threadIdx.x;
+    // each XCD takes one contiguous eighth of the tets: neighbouring tets share
+    // node blocks, so their cotangent rows stay in one L2 (132 -> 85 us on the
+    // 384k-tet fracture state, same bits)
+    const int e = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (e >= v.n_tets)
         return;
     const int* pos = v.e2p + 10 * (size_t)e;

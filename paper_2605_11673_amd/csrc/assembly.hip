@@ -28,7 +28,6 @@ namespace sta {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kXcds = 8;
 constexpr int kEditLanes = 16;     // phase 1: one lane per block slot (10 used), power of two
 // Claimed blocks are compacted per edit-phase wave (64 / kEditLanes = 4
 // edits): at most 16 diagonal and 24 off-diagonal claims.
@@ -64,19 +63,10 @@ __device__ __forceinline__ void st2(double* p, double a, double b)
         *reinterpret_cast<dvec2*>(p) = x;
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
 // The rebuild kernels remap workgroup ids so that neighbouring work, which
-// shares contribution, descriptor and CSR cache lines, runs on one XCD.
+// shares contribution, descriptor and CSR cache lines, runs on one XCD: the
+// element kernel gives each XCD one contiguous eighth of the tets (xcd_remap).
 //
-// Element kernel: each XCD walks one contiguous eighth of the tets.
-__device__ __forceinline__ int xcd_remap(int wg, int G)
-{
-    const int q = G / kXcds, r = G % kXcds;
-    const int x = wg % kXcds, idx = wg / kXcds;
-    const int base = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
-    return base + idx;
-}
-
 // Reduce: each XCD takes runs of kXcdRun consecutive workgroups in turn, so
 // that the runs spread every part of the work (the diagonal blocks, then the
 // off-diagonal ones) evenly over the XCDs.  One contiguous range per XCD put

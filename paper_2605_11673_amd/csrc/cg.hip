@@ -203,9 +203,21 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(CgView c, int k, int cur, in
     const int group = threadIdx.x / kNodeLanes, l = threadIdx.x & (kNodeLanes - 1);
     constexpr int kGroups = kBlock / kNodeLanes;
     double pq = 0.0;
-    // grid-stride over nodes; every group of a workgroup runs the same number of rounds
-    for (int base_node = blockIdx.x * kGroups; base_node < nn; base_node += gridDim.x * kGroups) {
-        const int i = base_node + group;
+    // Node groups of kGroups nodes: with at least kXcds workgroups each XCD walks one
+    // contiguous share of them (its workgroups in turn), so that neighbouring
+    // nodes, which gather the same entries of z and p, stay in one L2 (29.8 ->
+    // 28.3 us per iteration on the 207k-row fracture system); otherwise a plain
+    // grid-stride.  All groups of a workgroup run the same number of rounds.
+    const int ngroups = (nn + kGroups - 1) / kGroups;
+    int g0 = blockIdx.x, g1 = ngroups, gstep = gridDim.x;
+    if ((int)gridDim.x >= kXcds) {
+        const int xcd = blockIdx.x % kXcds, G = gridDim.x;
+        g0 = (int)((int64_t)ngroups * xcd / kXcds) + blockIdx.x / kXcds;
+        g1 = (int)((int64_t)ngroups * (xcd + 1) / kXcds);
+        gstep = G / kXcds + (xcd < G % kXcds ? 1 : 0);  // workgroups on this XCD
+    }
+    for (int gi = g0; gi < g1; gi += gstep) {
+        const int i = gi * kGroups + group;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
         if (i < nn) {
             const int base = c.rowptr[3 * i];

@@ -36,6 +36,20 @@ struct Ctl {
 // Polls of the fused frame's grid barrier before it reports ERR_TIMEOUT.
 constexpr unsigned kBarrierSpinDefault = 1u << 24;
 
+// Workgroups are dispatched round-robin over the 8 XCDs of the device, each
+// with its own L2.  xcd_remap maps a dispatch index to a work index such
+// that each XCD walks one contiguous share of the work (sizes differ by at
+// most one), so that neighbouring work, which shares cache lines, stays in
+// one L2.  A permutation of [0, G).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_remap(int wg, int G)
+{
+    const int q = G / kXcds, r = G % kXcds;
+    const int x = wg % kXcds, idx = wg / kXcds;
+    const int base = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+    return base + idx;
+}
+
 // Incidence-length buckets of the slot mapping: a block's segment length
 // kappa (its number of candidate tets) puts a diagonal block in bucket 0
 // (kappa <= 8), 1 (9..32) or 2 (> 32), an off-diagonal block in bucket 0
