@@ -292,11 +292,7 @@ sta_status build_context(const double* x, int64_t n_nodes, const int32_t* tets, 
                 r.desc[j] = hd[he2b[10 * t + j]];
                 r.pos[j] = P.e2p[10 * t + j];
             }
-            for (int a = 0; a < 4; ++a)
-                for (int k = 0; k < 3; ++k)
-                    r.X[3 * a + k] = x[3 * (int64_t)tets[4 * t + a] + k];
             r.T = hT[t];
-            r.E = E[t];
         }
         if (e == hipSuccess) e = upload(trec, hr.data(), hr.size(), s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);  // hr is freed at the end of this block
@@ -328,6 +324,8 @@ sta_status build_context(const double* x, int64_t n_nodes, const int32_t* tets, 
     v.wg_err = wg_err;
     v.ctl = ctl;
 
+    // the records' geometry, computed on the device with the element kernel's routine
+    if (e == hipSuccess) e = launch_refresh_records(v, trec, s);
     if (e == hipSuccess) e = launch_element(v, false, s);
     if (e == hipSuccess) e = launch_reduce_all(v, c->rebuild_map, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -654,8 +654,8 @@ __device__ __forceinline__ int edit_lane(const DevView& v, int id, unsigned st, 
     const bool slot = r < 10;
     const TetRecord* rc = v.trec + id;
     // round trip 1: the tet's record (this lane's block descriptor and
-    // incidence position; vertex ids, coordinates and modulus for an
-    // activation), its mask bit and its stamp
+    // incidence position; vertex ids and geometry for an activation), its
+    // mask bit and its stamp
     BlockDesc bd = empty_desc();
     int ep = 0;
     if (slot) {
@@ -663,18 +663,21 @@ __device__ __forceinline__ int edit_lane(const DevView& v, int id, unsigned st, 
         ep = rc->pos[r];
     }
     int4 t = make_int4(0, 0, 0, 0);
-    double E = 0.0;
-    double X[4][3];
+    Geo G;
     if (slot && st) {
         t = rc->T;
-        E = rc->E;
-        const dvec2* xp = reinterpret_cast<const dvec2*>(rc->X);
+        const dvec2* gp = reinterpret_cast<const dvec2*>(rc->g);
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            const dvec2 q = xp[k];
-            X[(2 * k) / 3][(2 * k) % 3] = q.x;
-            X[(2 * k + 1) / 3][(2 * k + 1) % 3] = q.y;
+            const dvec2 q = gp[k];
+            G.g[(2 * k) / 3][(2 * k) % 3] = q.x;
+            G.g[(2 * k + 1) / 3][(2 * k + 1) % 3] = q.y;
         }
+        const dvec2 lm = *reinterpret_cast<const dvec2*>(&rc->lamV);
+        G.lamV = lm.x;
+        G.muV = lm.y;
+        G.ml = rc->ml;
+        G.det = rc->degenerate ? 0.0 : 1.0;  // store_slot only tests det == 0
     }
     const uint8_t prev = v.mask[id];
     unsigned taken = 0u;
@@ -696,12 +699,8 @@ __device__ __forceinline__ int edit_lane(const DevView& v, int id, unsigned st, 
     } else if (change) {
         if (r == 0)
             v.mask[id] = (uint8_t)st;
-        if (slot) {
-            Geo G;
-            if (st)
-                geometry_from(v, X, E, G);
+        if (slot)
             store_slot(v, t, G, r, ep, st != 0u);
-        }
     }
     // the claim is consumed last, so the claim's round trip overlaps the slot
     // arithmetic; the caller compacts the wave's claims into its region
@@ -1154,20 +1153,25 @@ __global__ __launch_bounds__(kBlock) void k_set_params(int n_nodes, int n_tets, 
         Eout[i] = Ein[i];
 }
 
+// The geometry part of every tet record, from the current coordinates and
+// moduli, by the rebuild's own routine (element_geometry).
 __global__ __launch_bounds__(kBlock) void k_refresh_records(DevView v, TetRecord* __restrict__ trec)
 {
     const int e = blockIdx.x * kBlock + threadIdx.x;
     if (e >= v.n_tets)
         return;
-    const int4 t = v.T[e];
-    const int id[4] = {t.x, t.y, t.z, t.w};
+    Geo G;
+    element_geometry(v, e, v.T[e], G);
+    TetRecord& rc = trec[e];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        trec[e].X[3 * a + 0] = v.xs[id[a]];
-        trec[e].X[3 * a + 1] = v.ys[id[a]];
-        trec[e].X[3 * a + 2] = v.zs[id[a]];
-    }
-    trec[e].E = v.E[e];
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            rc.g[3 * a + i] = G.g[a][i];
+    rc.lamV = G.lamV;
+    rc.muV = G.muV;
+    rc.ml = G.ml;
+    rc.degenerate = G.det == 0.0 ? 1 : 0;
 }
 
 inline unsigned blocks_for(int64_t threads)

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -112,17 +113,23 @@ struct BlockDesc {
 // Everything the edit phase reads about one candidate tet, packed in one
 // 512-byte record so that an edit needs a single memory round trip before
 // its atomics: the tet's 10 block descriptors (local pairs 00 11 22 33 | 01
-// 02 03 12 13 23), its vertex coordinates and modulus (copies, refreshed by
-// sta_set_params), its vertex ids and its 10 incidence positions.
+// 02 03 12 13 23), its geometry as the element formula uses it (basis
+// gradients g_0..g_3, lamV, muV and the lumped mass per vertex, computed on
+// the device by the same routine as the rebuild's, so an activation
+// reproduces the rebuild's bits without redoing the determinant and the
+// inverse; refreshed by sta_set_params), a flag for det == 0, its vertex ids
+// and its 10 incidence positions.
 struct TetRecord {
     BlockDesc desc[10];
-    double X[12];
+    double g[12];  // g_a component i at 3a + i
     int4 T;
-    double E;
+    double lamV, muV, ml;  // lamV at a 16-byte boundary (read with muV as one 16-byte load)
     int32_t pos[10];
-    int32_t pad[8];
+    int32_t degenerate;  // det == 0
+    int32_t pad[3];
 };
 static_assert(sizeof(TetRecord) == 512, "tet record is 512 bytes");
+static_assert(offsetof(TetRecord, lamV) % 16 == 0, "lamV and muV are read as one 16-byte load");
 
 // Everything the kernels need, passed by value.
 //
