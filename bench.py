@@ -42,7 +42,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "per-frame A_t update us + touched slots/s, streaming vs GPU rebuild; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2605_11673_amd", "csrc", "assembly.hip")
+CSRC = os.path.join(ROOT, "paper_2605_11673_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -140,36 +140,46 @@ def pct(a, q):
 
 
 def source_sha():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Digest of every kernel source: counter records taken with other sources are not used."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
 
 
-def load_traffic(kernel):
-    """HBM bytes per launch from committed rocprofv3 counter runs of the same
-    workload, or None if the kernel source changed since they were taken."""
-    try:
-        with open(TRAFFIC_FILE) as f:
-            d = json.load(f)
-    except (OSError, ValueError):
+_TRAFFIC = None
+
+
+def _traffic():
+    global _TRAFFIC
+    if _TRAFFIC is None:
+        try:
+            with open(TRAFFIC_FILE) as f:
+                d = json.load(f)
+        except (OSError, ValueError):
+            d = {}
+        _TRAFFIC = d if d.get("source_sha") == source_sha() else {}
+    return _TRAFFIC
+
+
+def load_traffic(workload, kernels, per=None):
+    """HBM bytes (FETCH_SIZE + WRITE_SIZE, scaled) from the committed rocprofv3 counter runs
+    of `workload`: the kernels' summed bytes per unit, a unit being one dispatch of `per`
+    (default: of the first kernel).  None if a kernel has no record or the kernel sources
+    changed since the counters were taken."""
+    rec = _traffic().get("workloads", {}).get(workload, {}).get("kernels", {})
+    if not all(k in rec for k in kernels) or (per is not None and per not in rec):
         return None
-    rec = d.get("kernels", {}).get(kernel)
-    if not rec or d.get("source_sha") != source_sha():
-        return None
-    return rec
+    units = rec[per or kernels[0]]["dispatches"]
+    return round(sum(rec[k]["bytes"] for k in kernels) / max(units, 1), 1)
 
 
 def load_frame_traffic(touched_kernel):
-    """Per-frame HBM bytes of the two streaming kernels from the committed counter runs
-    (first pass over the headline step), or None if the kernel source changed since or the
-    counters were taken with another phase-2 instantiation than `touched_kernel`."""
-    try:
-        with open(TRAFFIC_FILE) as f:
-            d = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if d.get("source_sha") != source_sha() or d.get("frames_touched_kernel") != touched_kernel:
-        return None
-    return d.get("frames")
+    """Per-frame HBM bytes of the two streaming kernels (first pass over the headline step,
+    phase 2 as the instantiation `touched_kernel`), or None."""
+    return _traffic().get("frames", {}).get(touched_kernel)
 
 
 def kernel_instance(asm, kernel):
@@ -190,15 +200,14 @@ def kernel_instance(asm, kernel):
     return kernel
 
 
-def roofline(kernel, alg_bytes, seconds, launches, traffic_key=None, with_traffic=True, design_bytes=None):
+def roofline(kernel, alg_bytes, seconds, launches, traffic=None, design_bytes=None):
     """alg_bytes: the method's algorithmic bytes over all launches; design_bytes (optional):
-    the design's own byte count over the same launches, reported beside it.  with_traffic:
-    attach the committed counter traffic (taken on the headline workload only)."""
+    the design's own byte count over the same launches, reported beside it; traffic: the
+    counted HBM bytes per launch (load_traffic), or None."""
     achieved = alg_bytes / seconds / 1e9 if seconds > 0 else 0.0
-    tr = load_traffic(traffic_key or kernel) if with_traffic else None
     out = {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-           "traffic": None if tr is None else tr.get("bytes_per_launch"),
+           "traffic": traffic,
            "algorithmic_bytes_per_launch": round(alg_bytes / max(launches, 1), 1),
            "avg_launch_us": round(seconds / max(launches, 1) * 1e6, 3), "launches": launches}
     if design_bytes is not None:
@@ -243,10 +252,10 @@ def host_info():
 class Stream:
     """An assembler, its step (a list of device-resident frames) and per-frame stats."""
 
-    def __init__(self, torch, asm, frames, n_tets, n_nodes, mask0, headline=True):
+    def __init__(self, torch, asm, frames, n_tets, n_nodes, mask0, workload="fracture"):
         from paper_2605_11673_amd import stafem
         self.torch, self.asm = torch, asm
-        self.headline = headline  # the committed counter traffic belongs to the headline workload
+        self.workload = workload  # key of this workload's counter records
         self.frames_host = frames
         self.dframes = [stafem.upload_frame(ids, st) for ids, st in frames]
         self.n_tets, self.n_nodes, self.mask0 = n_tets, n_nodes, mask0
@@ -328,7 +337,7 @@ class Stream:
         alg = steps * sum(ALG_MODEL[dom](st) for st in self.stats)
         des = steps * sum(design[dom](st) for st in self.stats)
         return kern, roofline("k_" + dom, alg, ktimes[dom][1] * 1e-3, ktimes[dom][0],
-                              traffic_key=kernel_instance(self.asm, "k_" + dom), with_traffic=self.headline,
+                              traffic=load_traffic(self.workload, [kernel_instance(self.asm, "k_" + dom)]),
                               design_bytes=des)
 
     def rebuild_pipelined(self, reps=20):
@@ -371,9 +380,9 @@ class Stream:
         n_e, ms_e = kt.get("element", (0, 0.0))
         n_r, ms_r = kt.get("reduce", (0, 0.0))
         return {"element": roofline("k_element", eb * n_e, ms_e * 1e-3, n_e,
-                                    traffic_key=kernel_instance(asm, "k_element"), with_traffic=self.headline),
+                                    traffic=load_traffic(self.workload, [kernel_instance(asm, "k_element")])),
                 "reduce": roofline("k_reduce_all", rb * n_r, ms_r * 1e-3, n_r,
-                                   traffic_key=kernel_instance(asm, "k_reduce_all"), with_traffic=self.headline),
+                                   traffic=load_traffic(self.workload, [kernel_instance(asm, "k_reduce_all")])),
                 "rebuild_us_mean": round((ms_e + ms_r) * 1e3 / max(n_r, 1), 3),
                 "full_rebuild_alg_bytes": int(eb + rb)}
 
@@ -406,7 +415,7 @@ class Stream:
             return ev[0].elapsed_time(ev[1]) * 1e3
 
         rows, t_stream, t_cold, t_reb, t_reb_cold = [], [], [], [], []
-        ftr = load_frame_traffic(kernel_instance(asm, "k_touched")) if self.headline else None
+        ftr = load_frame_traffic(kernel_instance(asm, "k_touched")) if self.workload == "fracture" else None
         for k, ((di, ds), st) in enumerate(zip(self.dframes, self.stats)):
             ids_h = self.frames_host[k][0]
             prev = torch.from_numpy(self.mask_before(k)[ids_h].copy()).cuda()  # undoes the frame
@@ -494,13 +503,18 @@ def cpu_baseline(args, w, frames, stats):
                           "sample": "the same frames, row-parallel oracle rebuild on every host thread"}}
 
 
-def secondary(torch, name, asm, frames, n_tets, n_nodes, mask0, peak, args, describe, fused_too=False):
+def secondary(torch, name, asm, frames, n_tets, n_nodes, mask0, peak, args, describe, fused_too=False,
+              workload=None):
     """Tuned, parity-checked, graph-timed stream of another workload; with fused_too the
     same stream also in the one-launch frame mode (the tuned slot mapping, its own parity
     check and timing)."""
     log(f"[bench] {name}: {n_tets} tets, {len(frames)} frames")
-    s = Stream(torch, asm, frames, n_tets, n_nodes, mask0, headline=False)
-    cfg, _ = s.tune(peak)
+    s = Stream(torch, asm, frames, n_tets, n_nodes, mask0, workload=workload)
+    if args.config:  # forced (as for counter runs, where the tuner's repeated frames would skew averages)
+        asm.set_config(*[int(v) for v in args.config.split(",")])
+        cfg = {**asm.get_config(), "buckets": {k: asm.bucket_map(k) for k in ("rebuild", "stream")}}
+    else:
+        cfg, _ = s.tune(peak)
     stats, mism = s.stats_pass(check_parity=True)
     steps = max(3, args.steps // 4)
     kt, eager_s, step_s = s.timed(steps, 1)
@@ -624,7 +638,8 @@ def proxy_section(torch, stafem, w, frames, args):
            "rebuild_us_median": round(reb_us, 3),
            "rebuild_roofline": {"bound": "hbm", "achieved": round(alg / (reb_us * 1e-6) / 1e9, 2), "peak": HBM_PEAK_GBS,
                                 "unit": "GB/s", "frac": round(alg / (reb_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5),
-                                "traffic": None, "algorithmic_bytes": alg},
+                                "traffic": load_traffic("proxy", ["k_proxy_counts", "k_proxy_diagonal"]),
+                                "algorithmic_bytes": alg},
            "rebuild_vs_pipelined_frame": round(reb_us / (step_s * 1e6 / frames_per_step), 2),
            "parity": {"frames_checked": len(frames), "mismatching_frames": mism,
                       "check": "streaming counts, degrees and values bitwise equal to a GPU rebuild at every frame"}}
@@ -718,7 +733,8 @@ def delta_section(torch, stafem, w, frames, cfg, exact_step_s, args, stats=None,
         asm.enable_kernel_timing(False)
         n_d, ms_d = kt.get("delta", (0, 0.0))
         out["roofline"] = roofline("k_delta_edits+k_delta_clear", sum(bytes_delta(st) for st in stats),
-                                   ms_d * 1e-3, n_d, with_traffic=False)
+                                   ms_d * 1e-3, n_d,
+                                   traffic=load_traffic("delta", ["k_delta_edits", "k_delta_clear"]))
     if oracle_s_per_frame:
         out["cpu_baseline"] = {"value": round(oracle_s_per_frame * 1e6, 1), "unit": "us per frame", "cores": 1,
                                "kind": "oracle",
@@ -817,7 +833,7 @@ def euler_section(torch, stafem, workloads, w, frames, cfg, args, rtol=1e-8):
            "trajectories_bitwise_equal": bool(same)}
     ms_cg, it_cg, n_rows, nnz = cg["stream"]
     out["roofline"] = roofline("cg_iteration", bytes_cg_iteration(n_rows, nnz) * it_cg, ms_cg * 1e-3, it_cg,
-                               with_traffic=False)
+                               traffic=load_traffic("euler", ["k_cg_spmv", "k_cg_update"], per="k_cg_update"))
     if not args.no_cpu_baseline:
         # the oracle's step of eq. (9) at the frame-12 state: its matrix, lumped mass and PCG
         import oracle
@@ -894,10 +910,13 @@ def gradient_section(torch, stafem, workloads, args, rtol=1e-10, reps=5):
            "active_tets": int(mask.sum()),
            "cg": {"rtol": rtol, "iterations": it, "relres": rr, "us_per_iteration": round(it_us, 3),
                   "roofline": roofline("cg_iteration", cg_bytes * iters, ms_solve * 1e-3, iters,
-                                       with_traffic=False)},
+                                       traffic=load_traffic("gradient", ["k_cg_spmv", "k_cg_update"],
+                                                            per="k_cg_update"))},
            "adjoint": {"us": round(ms_adj * 1e3 / max(n_adj, 1), 3),
                        "roofline": roofline("k_adjoint_element+k_adjoint_nodes", adj_bytes * n_adj,
-                                            ms_adj * 1e-3, n_adj, with_traffic=False)}}
+                                            ms_adj * 1e-3, n_adj,
+                                            traffic=load_traffic("gradient", ["k_adjoint_element",
+                                                                              "k_adjoint_nodes"]))}}
     if not args.no_cpu_baseline:
         # the CPU baseline leg: the oracle's complex-step adjoint on the same cotangents and
         # its PCG on the same system, timed on the host; the GPU gradient is compared with
@@ -931,6 +950,17 @@ def gradient_section(torch, stafem, workloads, args, rtol=1e-10, reps=5):
     return out
 
 
+def face_pair_count(tets):
+    """Candidate tet pairs with a common face (for the face-adjacency byte count): every pair
+    of tets on one sorted vertex triple."""
+    tri = np.sort(tets.astype(np.int64), axis=1)
+    faces = np.concatenate([tri[:, [1, 2, 3]], tri[:, [0, 2, 3]], tri[:, [0, 1, 3]], tri[:, [0, 1, 2]]])
+    n = int(tri.max()) + 1
+    key = (faces[:, 0] * n + faces[:, 1]) * n + faces[:, 2]
+    _, counts = np.unique(key, return_counts=True)
+    return int((counts * (counts - 1) // 2).sum())
+
+
 # Connectivity is rebuilt from the mask periodically (paper Sec. 3.6), with no period given:
 # here once per 4 frames, the frames per scenario of the paper's elasticity study (Sec. 5).
 CONNECTIVITY_PERIOD = 4
@@ -948,7 +978,10 @@ def connectivity_section(torch, stafem, w, frames, args):
 
     lib = stafem.load()
     fns = {"vertex": lib.sta_components, "face": lib.sta_face_components}
-    asm.components("face")  # the face pairs are found once per context, outside the timing
+    if args.adjacency != "both":
+        fns = {args.adjacency: fns[args.adjacency]}
+    if "face" in fns:
+        asm.components("face")  # the face pairs are found once per context, outside the timing
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     res = {a: {"times": [], "counts": [], "stable": True} for a in fns}
     for ids, st in dfr:
@@ -967,7 +1000,7 @@ def connectivity_section(torch, stafem, w, frames, args):
             again, k = asm.components(adj)
             r["stable"] = r["stable"] and bool(torch.equal(again, lab))
             r["counts"].append(k)
-    n_pairs = 0  # candidate face pairs, counted in the CPU-baseline leg
+    n_pairs = face_pair_count(w.tets)
     asm.close()
     period = CONNECTIVITY_PERIOD
     out = {"workload": "components of the active tets rebuilt after every frame of the headline stream, "
@@ -984,7 +1017,6 @@ def connectivity_section(torch, stafem, w, frames, args):
         C.components(w.n_nodes, w.tets, mask)
         oracle_s["vertex"] = time.perf_counter() - t0
         pairs = C.face_pairs(w.tets)
-        n_pairs = len(pairs)
         t0 = time.perf_counter()
         C.face_components(w.tets, mask, pairs)
         oracle_s["face"] = time.perf_counter() - t0
@@ -998,8 +1030,11 @@ def connectivity_section(torch, stafem, w, frames, args):
                     "us_per_frame_at_period": round(med / period, 3)}
         if adj == "vertex" or n_pairs:
             nb = bytes_connectivity_pass(w.n_tets, w.n_nodes, n_pairs if adj == "face" else 0)
+            ks = (["k_cc_seed", "k_cc_shortcut", "k_cc_hook", "k_cc_label", "k_cc_count"] if adj == "vertex"
+                  else ["k_ccf_init", "k_ccf_seed", "k_ccf_hook", "k_cc_shortcut", "k_ccf_label"])
             out[adj]["roofline"] = roofline(f"connectivity ({adj}), one-pass lower bound", nb, med * 1e-6, 1,
-                                            with_traffic=False)
+                                            traffic=load_traffic(f"connectivity_{adj}", ks, per=ks[3 if adj == "vertex"
+                                                                                                      else 4]))
         if adj in oracle_s:
             out[adj]["cpu_baseline"] = {"value": round(oracle_s[adj] * 1e6, 1), "unit": "us per rebuild",
                                         "cores": 1, "kind": "oracle",
@@ -1009,6 +1044,9 @@ def connectivity_section(torch, stafem, w, frames, args):
         log(f"[bench] connectivity ({adj}): {out[adj]['rebuild_us_median']} us per rebuild, components "
             f"{c[0]} -> {max(c)} -> {c[-1]}")
     return out
+
+
+SECTIONS = ("delta", "proxy", "euler", "connectivity", "gradient", "refinement", "batch")
 
 
 def compact_line(out, detail_path):
@@ -1071,7 +1109,7 @@ def compact_line(out, detail_path):
         c = out["connectivity"]
         sec["connectivity"] = {a: {"rebuild_us": c[a]["rebuild_us_median"],
                                    "us_per_frame_at_period": c[a]["us_per_frame_at_period"]}
-                               for a in ("vertex", "face")}
+                               for a in ("vertex", "face") if a in c}
         sec["connectivity"]["period_frames"] = c["period_frames"]
     if sec:
         line["sections"] = sec
@@ -1093,6 +1131,11 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--adjacency", default="both", choices=("both", "vertex", "face"),
+                    help="connectivity section: which adjacencies to rebuild")
+    ap.add_argument("--sections", default="all",
+                    help="secondary sections to run: all, or a comma list of " + ",".join(SECTIONS)
+                         + " (with --quick, only the named ones; default none)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default configuration")
     ap.add_argument("--config", default=None,
                     help="force fused,rebuild_qd,rebuild_qo,stream_qd,stream_qo,grid_cap,rebuild_nt (skips tuning)")
@@ -1171,6 +1214,8 @@ def main():
         del src, dst
     if not args.quick:
         out["latency_floor"] = stafem.latency_probe()
+        out["barrier_vs_boundary"] = stafem.barrier_probe()
+        log(f"[bench] grid barrier vs kernel boundary (us per graph-replayed unit): {out['barrier_vs_boundary']}")
         out["hbm_measured"] = {k: round(x, 1) for k, x in stafem.bandwidth_probe().items()}
         rr = s.rebuild_roofline()
         rb = rr["element"]["algorithmic_bytes_per_launch"] + rr["reduce"]["algorithmic_bytes_per_launch"]
@@ -1203,13 +1248,27 @@ def main():
         log(f"[bench] cpu baseline: {cb['rebuild_s_per_frame']} s per oracle rebuild (1 thread), "
             f"{cb['multicore']['rebuild_s_per_frame']} s on {cb['multicore']['cores']} threads "
             f"(bitwise equal: {cb['multicore']['bitwise_equal_to_serial']}); {cb['cpu_model']}, nproc {cb['nproc']}")
-    if not args.quick and not args.no_extras:
+    if args.sections == "all":
+        sections = [] if (args.quick or args.no_extras) else list(SECTIONS)
+    else:
+        sections = [x for x in args.sections.split(",") if x]
+        bad = [x for x in sections if x not in SECTIONS]
+        if bad:
+            raise SystemExit(f"unknown sections {bad}; choose from {SECTIONS}")
+        if args.no_extras:
+            sections = []
+    if "delta" in sections:
         out["delta"] = delta_section(torch, stafem, w, frames, out["tuned_config"], step_s, args, stats,
                                      out.get("cpu_baseline", {}).get("rebuild_s_per_frame"))
+    if "proxy" in sections:
         out["proxy"] = proxy_section(torch, stafem, w, frames, args)
+    if "euler" in sections:
         out["euler"] = euler_section(torch, stafem, workloads, w, frames, out["tuned_config"], args)
+    if "connectivity" in sections:
         out["connectivity"] = connectivity_section(torch, stafem, w, frames, args)
+    if "gradient" in sections:
         out["gradient"] = gradient_section(torch, stafem, workloads, args)
+    if "refinement" in sections:
         r = workloads.make_refinement(args.seed)
         rf = r.frames[:24]
         rframes = rf + [(ids, (1 - st).astype(np.uint8)) for ids, st in reversed(rf)]
@@ -1219,8 +1278,9 @@ def main():
                                       r.mask0, peak, args,
                                       "red-refinement superset 432000 tets (48000 parents + 8 children each), "
                                       "24 refine frames (0.1-2% of parents swapped for children) then the same "
-                                      "swaps undone in reverse (merge), FP64")
+                                      "swaps undone in reverse (merge), FP64", workload="refinement")
         ra.close()
+    if "batch" in sections:
         ws = workloads.make_batch(args.seed)
         b = stafem.Batch.from_workloads(ws)
         off = b.offsets()["tet"]
@@ -1234,7 +1294,7 @@ def main():
         out["batch"] = secondary(torch, "batch of 64 meshes", b, bframes, b.n_tets, b.n_nodes, mask0, 12, args,
                                  f"64 jittered Kuhn cubes of 6n^3 tets (n log-uniform, {b.n_tets} tets in all), "
                                  "each with its own 24-frame fracture stream, then reinsertion; one context, "
-                                 "one frame = all meshes' edits, FP64", fused_too=True)
+                                 "one frame = all meshes' edits, FP64", fused_too=True, workload="batch")
         b.close()
     if args.detail:
         d = os.path.dirname(args.detail)

@@ -66,7 +66,10 @@ typedef int sta_status;
 
 #define STA_OK 0
 #define STA_EINVAL (-1)       /* bad argument (null pointer, size, material) */
-#define STA_ENOMEM (-2)       /* device or host allocation failed */
+#define STA_ENOMEM (-2)       /* device or host allocation failed (tests can force it: with the
+                                 environment variable STA_FAIL_ALLOC_AT=k the k-th device
+                                 allocation of the library fails; the call frees what it had
+                                 allocated and changes nothing) */
 #define STA_EHIP (-3)         /* a HIP runtime call failed */
 #define STA_EDEGENERATE (-4)  /* a candidate tet has det == 0 or a repeated node */
 #define STA_ESTALE (-5)       /* parameters changed; call sta_full_rebuild first */
@@ -297,6 +300,16 @@ sta_status sta_set_config(sta_ctx* ctx, int fused, int rebuild_qd, int rebuild_q
                           int grid_cap, int rebuild_nt);
 sta_status sta_get_config(const sta_ctx* ctx, int* out7);
 
+/* Audit of the maintained state against the Sec. 3.3 invariant (the
+ * maintained matrix equals a rebuild from the mask), without changing it:
+ * out2[1] = tets whose 78 stored contribution slots differ in any bit from
+ * what a rebuild would store (the element matrix of an active tet, +0.0 for
+ * an inactive one); out2[0] = matrix values differing in any bit from a
+ * re-sum of the stored contributions into a scratch copy (nnz doubles,
+ * allocated on first use).  Both 0 for an intact context.  Synchronises
+ * `stream`.  STA_ESTALE after sta_set_params until a rebuild. */
+sta_status sta_audit(sta_ctx* ctx, void* stream, int64_t* out2);
+
 /* Failure injection for the fused frame (tests of STA_ETIMEOUT): the grid
  * barrier between the two phases gives up after `polls` polls of its
  * release word (0 restores the default, 2^24, far beyond any co-resident
@@ -374,6 +387,16 @@ sta_status sta_latency_probe(void* stream, double* out4);
  * kernels are reported against the published 8 TB/s peak; these numbers
  * say what a plain streaming kernel reaches on the same device. */
 sta_status sta_bandwidth_probe(void* stream, double* out3);
+
+/* Cost of a grid barrier against a kernel boundary on this GPU (no context
+ * needed; creates its own stream, allocates a few bytes, synchronises):
+ * microseconds per unit with each unit captured 50 times into a HIP graph
+ * and the graph replayed, out7[0] = one empty kernel, out7[1] = two empty
+ * kernels (the boundary a two-launch frame pays), out7[2..6] = one kernel of
+ * 8, 32, 64, 128, 256 workgroups that does nothing but the fused frame's grid
+ * barrier (-1 where that grid would not be co-resident).  STA_ETIMEOUT if a
+ * barrier gave up. */
+sta_status sta_barrier_probe(double* out7);
 
 /* Synchronise `stream`, return and clear the first error the device
  * recorded (STA_ETIMEOUT, STA_ERANGE, STA_EDUP, STA_EDEGENERATE), else

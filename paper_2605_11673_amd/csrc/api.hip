@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -28,6 +29,22 @@ sta_status hip_fail(sta_ctx* ctx, hipError_t e, const char* what)
     return fail(ctx, STA_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Failure injection for tests of STA_ENOMEM: when the environment variable
+// STA_FAIL_ALLOC_AT is a number k >= 1, the k-th device allocation made by
+// this process (counting from the first allocation after the variable is
+// read as set) reports out-of-memory without allocating.
+bool injected_alloc_failure()
+{
+    static thread_local long seen = 0;
+    const char* at = std::getenv("STA_FAIL_ALLOC_AT");
+    if (!at || !*at) {
+        seen = 0;
+        return false;
+    }
+    const long k = std::strtol(at, nullptr, 10);
+    return k >= 1 && ++seen == k;
+}
+
 template <class T>
 hipError_t dalloc(sta_ctx* c, T** p, size_t count)
 {
@@ -35,6 +52,8 @@ hipError_t dalloc(sta_ctx* c, T** p, size_t count)
     size_t bytes = count * sizeof(T);
     if (bytes == 0)
         bytes = 256;
+    if (injected_alloc_failure())
+        return hipErrorOutOfMemory;
     hipError_t e = hipMalloc(&q, bytes);
     if (e == hipSuccess) {
         c->owned.push_back(q);
@@ -701,6 +720,38 @@ sta_status sta_get_config(const sta_ctx* ctx, int* out7)
     out6[4] = ctx->stream_map.qo;
     out6[5] = ctx->frame_grid_cap;
     out6[6] = ctx->rebuild_map.nt;
+    return STA_OK;
+}
+
+sta_status sta_audit(sta_ctx* ctx, void* stream, int64_t* out2)
+{
+    if (!ctx || !out2)
+        return STA_EINVAL;
+    if (ctx->stale)
+        return fail(ctx, STA_ESTALE, "parameters changed: call sta_full_rebuild before sta_audit");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (!ctx->audit_ws) {
+        // nnz doubles, then two 8-byte counters (the allocation is 256-byte aligned)
+        e = dalloc(ctx, &ctx->audit_ws, (size_t)ctx->nnz + 2);
+        if (e != hipSuccess) {
+            ctx->audit_ws = nullptr;
+            return fail(ctx, STA_ENOMEM, "audit workspace allocation failed");
+        }
+    }
+    unsigned long long* counts = reinterpret_cast<unsigned long long*>(ctx->audit_ws + ctx->nnz);
+    e = hipMemsetAsync(counts, 0, 2 * sizeof(unsigned long long), s);
+    if (e == hipSuccess)
+        e = launch_audit(ctx->v, ctx->rebuild_map, ctx->audit_ws, ctx->nnz, counts, s);
+    unsigned long long h[2] = {0, 0};
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h, counts, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "audit");
+    out2[0] = (int64_t)h[0];
+    out2[1] = (int64_t)h[1];
     return STA_OK;
 }
 

@@ -1046,41 +1046,6 @@ __global__ __launch_bounds__(kBlock) void k_delta_clear(DevView v, const int32_t
     }
 }
 
-// Grid-wide barrier for a co-resident grid (the host sizes the grid from the
-// occupancy so that every workgroup is resident).  The spin is bounded (at
-// most spin_limit polls): a grid that is not co-resident reports ERR_TIMEOUT
-// instead of hanging.
-
-__device__ __forceinline__ bool grid_barrier(Ctl* ctl, unsigned G, unsigned spin_limit, int* s_ok)
-{
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        const unsigned gen = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const unsigned arrived = atomicAdd(&ctl->bar_count, 1u);
-        if (arrived == G - 1) {
-            __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
-            __hip_atomic_fetch_add(&ctl->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            unsigned spins = 0;
-            while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins >= spin_limit) {
-                    ok = 0;
-                    atomicOr(&ctl->err, ERR_TIMEOUT);
-                    break;
-                }
-            }
-        }
-        __threadfence();
-        *s_ok = ok;
-    }
-    __syncthreads();
-    return *s_ok != 0;
-}
-
 // The whole frame in one persistent launch: phase 1 over the edits, grid
 // barrier, phase 2 over the claimed blocks (grid-stride loops; lane groups
 // stay aligned because the stride is a multiple of the workgroup size).
@@ -1126,6 +1091,77 @@ __global__ __launch_bounds__(kBlock) void k_frame(DevView v, const int32_t* __re
             touched_edit(v, ids[w], v.undo[w], fe);
         }
     }
+}
+
+// Audit: 1 if tet e's 78 stored contribution slots differ in any bit from
+// what the rebuild would store (its element matrix if active, +0.0 if not).
+__device__ __forceinline__ int audit_element(const DevView& v, int e)
+{
+    int pos[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j)
+        pos[j] = v.e2p[10 * (size_t)e + j];
+    const bool active = v.mask[e] != 0;
+    Geo G;
+    const int4 t = v.T[e];
+    if (active)
+        element_geometry(v, e, t, G);
+    const int id[4] = {t.x, t.y, t.z, t.w};
+    bool bad = false;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const double* c = v.cd + 6 * (size_t)pos[a];
+        double ga[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            ga[i] = active ? G.g[a][i] : 0.0;
+        const double s = dot3(ga, ga);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double want = active ? entry(ga, ga, s, G, kDiagP[k], kDiagQ[k], true) : 0.0;
+            bad = bad || __double_as_longlong(c[k]) != __double_as_longlong(want);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const bool sw = id[PA[q]] > id[PB[q]];
+        double ga[3], gb[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            ga[i] = active ? (sw ? G.g[PB[q]][i] : G.g[PA[q]][i]) : 0.0;
+            gb[i] = active ? (sw ? G.g[PA[q]][i] : G.g[PB[q]][i]) : 0.0;
+        }
+        const double s = dot3(ga, gb);
+        const double* c = v.co + 9 * (size_t)pos[4 + q];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double want = active ? entry(ga, gb, s, G, i, j, false) : 0.0;
+                bad = bad || __double_as_longlong(c[3 * i + j]) != __double_as_longlong(want);
+            }
+    }
+    return bad ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_audit_tets(DevView v, unsigned long long* count)
+{
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    const int bad = e < v.n_tets ? audit_element(v, e) : 0;
+    const uint64_t m = __ballot(bad != 0);
+    if ((threadIdx.x & 63) == 0 && m)
+        atomicAdd(count, (unsigned long long)__popcll(m));
+}
+
+// Audit: values whose bits differ between a and b.
+__global__ __launch_bounds__(kBlock) void k_audit_values(const double* __restrict__ a, const double* __restrict__ b,
+                                                         int64_t n, unsigned long long* count)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool bad = i < n && __double_as_longlong(a[i]) != __double_as_longlong(b[i]);
+    const uint64_t m = __ballot(bad);
+    if ((threadIdx.x & 63) == 0 && m)
+        atomicAdd(count, (unsigned long long)__popcll(m));
 }
 
 // Release every tet and block stamp (after a fused frame whose grid barrier
@@ -1323,6 +1359,26 @@ hipError_t launch_frame(const DevView& v, const MapConfig& m, int grid, const in
     STA_MAPPINGS(LAUNCH)
 #undef LAUNCH
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_audit(const DevView& v, const MapConfig& m, double* scratch_values, int64_t nnz,
+                        unsigned long long* counts, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    if (v.n_tets > 0) {
+        hipLaunchKernelGGL(k_audit_tets, dim3(blocks_for(v.n_tets)), dim3(kBlock), 0, s, v, counts + 1);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess || nnz == 0)
+        return e;
+    DevView w = v;
+    w.values = scratch_values;
+    e = launch_reduce_all(w, m, s);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_audit_values, dim3(blocks_for(nnz)), dim3(kBlock), 0, s, v.values, scratch_values, nnz,
+                       counts);
+    return hipGetLastError();
 }
 
 hipError_t launch_clear_stamps(const DevView& v, hipStream_t s)

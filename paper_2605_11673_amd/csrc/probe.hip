@@ -54,6 +54,13 @@ __global__ void k_atomic_chain(uint32_t* __restrict__ chase, int hops, uint64_t*
 
 __global__ void k_empty() {}
 
+// One grid barrier (the fused frame's, grid_barrier) and nothing else.
+__global__ __launch_bounds__(256) void k_barrier_only(Ctl* ctl, unsigned spin_limit)
+{
+    __shared__ int s_ok;
+    (void)grid_barrier(ctl, gridDim.x, spin_limit, &s_ok);
+}
+
 // Streaming bandwidth kernels: 16-byte accesses, consecutive lanes on
 // consecutive addresses, grid-stride over the buffer.
 typedef double dvec2 __attribute__((ext_vector_type(2)));
@@ -216,5 +223,87 @@ extern "C" sta_status sta_bandwidth_probe(void* stream, double* out3)
         return STA_EHIP;
     for (int k = 0; k < 3; ++k)
         out3[k] = res[k];
+    return STA_OK;
+}
+
+// Per-unit time of `launch` captured `per` times into one HIP graph on stream s
+// and replayed `reps` times, in microseconds.
+template <class F>
+static hipError_t graph_unit_us(hipStream_t s, int per, int reps, F&& launch, double* us)
+{
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    for (int i = 0; i < per && e == hipSuccess; ++i)
+        e = launch();
+    hipError_t e2 = hipStreamEndCapture(s, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(ge, s);  // warm-up
+    if (e == hipSuccess) e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipEventRecord(a, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r)
+        e = hipGraphLaunch(ge, s);
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    *us = ms * 1e3 / ((double)reps * per);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+}
+
+extern "C" sta_status sta_barrier_probe(double* out7)
+{
+    if (!out7)
+        return STA_EINVAL;
+    hipStream_t s = nullptr;
+    Ctl* ctl = nullptr;
+    int cus = 0, per_cu = 0, dev = 0;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&ctl, sizeof(Ctl));
+    if (e == hipSuccess) e = hipMemset(ctl, 0, sizeof(Ctl));
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_barrier_only, 256, 0);
+    const int per = 50, reps = 20;
+    double r[7];
+    for (int k = 0; k < 7; ++k)
+        r[k] = -1.0;
+    if (e == hipSuccess)
+        e = graph_unit_us(s, per, reps, [&] {
+            hipLaunchKernelGGL(k_empty, dim3(64), dim3(256), 0, s);
+            return hipGetLastError();
+        }, &r[0]);
+    if (e == hipSuccess)
+        e = graph_unit_us(s, per, reps, [&] {
+            hipLaunchKernelGGL(k_empty, dim3(64), dim3(256), 0, s);
+            hipLaunchKernelGGL(k_empty, dim3(64), dim3(256), 0, s);
+            return hipGetLastError();
+        }, &r[1]);
+    const int grids[5] = {8, 32, 64, 128, 256};
+    for (int k = 0; k < 5 && e == hipSuccess; ++k) {
+        if (grids[k] > cus * per_cu)
+            continue;  // not co-resident: not measured
+        e = graph_unit_us(s, per, reps, [&] {
+            hipLaunchKernelGGL(k_barrier_only, dim3(grids[k]), dim3(256), 0, s, ctl, kBarrierSpinDefault);
+            return hipGetLastError();
+        }, &r[2 + k]);
+    }
+    int32_t err = 0;
+    if (e == hipSuccess) e = hipMemcpy(&err, &ctl->err, sizeof(err), hipMemcpyDeviceToHost);
+    if (ctl) (void)hipFree(ctl);
+    if (s) (void)hipStreamDestroy(s);
+    if (e != hipSuccess)
+        return STA_EHIP;
+    if (err & ERR_TIMEOUT)
+        return STA_ETIMEOUT;
+    for (int k = 0; k < 7; ++k)
+        out7[k] = r[k];
     return STA_OK;
 }

@@ -37,6 +37,42 @@ struct Ctl {
 // Polls of the fused frame's grid barrier before it reports ERR_TIMEOUT.
 constexpr unsigned kBarrierSpinDefault = 1u << 24;
 
+// Grid-wide barrier for a co-resident grid (the host sizes the grid from the
+// occupancy so that every workgroup is resident).  The spin is bounded (at
+// most spin_limit polls): a grid that is not co-resident reports ERR_TIMEOUT
+// instead of hanging.
+
+__device__ __forceinline__ bool grid_barrier(Ctl* ctl, unsigned G, unsigned spin_limit, int* s_ok)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned gen = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const unsigned arrived = atomicAdd(&ctl->bar_count, 1u);
+        if (arrived == G - 1) {
+            __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            __hip_atomic_fetch_add(&ctl->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins >= spin_limit) {
+                    ok = 0;
+                    atomicOr(&ctl->err, ERR_TIMEOUT);
+                    break;
+                }
+            }
+        }
+        __threadfence();
+        *s_ok = ok;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+
 // Workgroups are dispatched round-robin over the 8 XCDs of the device, each
 // with its own L2.  xcd_remap maps a dispatch index to a work index such
 // that each XCD walks one contiguous share of the work (sizes differ by at
@@ -221,6 +257,7 @@ struct sta_ctx {
     double* tet_ml = nullptr;       // per tet: lumped mass per vertex dof, (rho V) / 4
     bool tet_ml_stale = true;
     double* euler_ws = nullptr;     // implicit Euler: M_t, right-hand side, new u (3 x n_rows)
+    double* audit_ws = nullptr;     // audit: nnz re-summed values, then 2 counters
     int32_t* cc_ws = nullptr;       // connectivity: parent and mark per node, 2 flags
     uint32_t* cc_host = nullptr;    // pinned flag read back after each pass
     int cc_passes = 0;              // passes of the last sta_components / sta_face_components
@@ -281,6 +318,11 @@ hipError_t frame_max_grid(const MapConfig& m, int device, int* max_grid);
 int frame_grid_for(const MapConfig& m, int32_t n_host, int max_grid, int grid_cap);
 hipError_t launch_frame(const DevView& v, const MapConfig& m, int grid, const int32_t* ids, const uint8_t* states,
                         int32_t n_host, const int32_t* n_dev, unsigned spin_limit, hipStream_t s);
+// Audit: counts[1] += tets whose stored contributions differ from the rebuild's,
+// then the blocks re-summed from the stored contributions into scratch_values
+// (nnz) and counts[0] += values differing from the maintained ones.
+hipError_t launch_audit(const DevView& v, const MapConfig& m, double* scratch_values, int64_t nnz,
+                        unsigned long long* counts, hipStream_t s);
 // Release every tet and block stamp (a fill kernel, so that it can be captured).
 hipError_t launch_clear_stamps(const DevView& v, hipStream_t s);
 hipError_t launch_set_params(const DevView& v, const double* x_aos, const double* E, double* xs, double* ys,

@@ -66,6 +66,7 @@ SIGNATURES = {
     "sta_set_config": (_int, [_vp, _int, _int, _int, _int, _int, _int, _int]),
     "sta_get_config": (_int, [_vp, ctypes.POINTER(_int)]),
     "sta_set_barrier_spin_limit": (_int, [_vp, _i64]),
+    "sta_audit": (_int, [_vp, _vp, _i64p]),
     "sta_set_bucket_map": (_int, [_vp, _int, _vp, _vp]),
     "sta_get_bucket_map": (_int, [_vp, _int, _vp, _vp, _vp]),
     "sta_autotune": (_int, [_vp, _vp, _vp, _i64, _int, _vp, ctypes.c_char_p, _i64]),
@@ -73,6 +74,7 @@ SIGNATURES = {
     "sta_batch_offsets": (_int, [_vp, ctypes.POINTER(_int), _vp, _vp, _vp, _vp, _i64]),
     "sta_latency_probe": (_int, [_vp, ctypes.POINTER(_dbl)]),
     "sta_bandwidth_probe": (_int, [_vp, ctypes.POINTER(_dbl)]),
+    "sta_barrier_probe": (_int, [ctypes.POINTER(_dbl)]),
     "sta_status_sync": (_int, [_vp, _vp]),
     "sta_last_error": (ctypes.c_char_p, [_vp]),
     "sta_destroy": (None, [_vp]),
@@ -335,6 +337,12 @@ class Assembler:
         _check(load().sta_get_config(self._ctx, out), self._ctx)
         return dict(zip(self.CONFIG, list(out)))
 
+    def audit(self, stream=None) -> dict:
+        """Compare the maintained state with a rebuild (sta_audit); synchronises."""
+        out = (ctypes.c_int64 * 2)()
+        _check(load().sta_audit(self._ctx, _stream_handle(stream), out), self._ctx)
+        return {"values_differing": int(out[0]), "tets_differing": int(out[1])}
+
     def set_barrier_spin_limit(self, polls: int):
         """Polls before the fused frame's grid barrier gives up (0: the default); a
         failure-injection aid for tests of STA_ETIMEOUT."""
@@ -523,6 +531,16 @@ def bandwidth_probe(stream=None) -> dict:
     out = (ctypes.c_double * 3)()
     _check(load().sta_bandwidth_probe(_stream_handle(stream), out), None)
     return {"read_GBs": out[0], "write_GBs": out[1], "copy_GBs": out[2]}
+
+
+def barrier_probe() -> dict:
+    """Grid barrier vs kernel boundary, microseconds per graph-replayed unit (see sta_barrier_probe)."""
+    out = (ctypes.c_double * 7)()
+    _check(load().sta_barrier_probe(out), None)
+    d = {"empty_kernel_us": out[0], "two_empty_kernels_us": out[1]}
+    for k, g in enumerate((8, 32, 64, 128, 256)):
+        d[f"barrier_kernel_{g}wg_us"] = out[2 + k] if out[2 + k] >= 0 else None
+    return d
 
 
 def latency_probe(stream=None) -> dict:

@@ -1,0 +1,82 @@
+"""Auxiliary subsystems on the GPU: the audit of the maintained state against a
+rebuild (paper Sec. 3.3 invariant), forced allocation failures (STA_ENOMEM, with
+nothing leaked), and the grid-barrier probe."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2605_11673_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def S():
+    from paper_2605_11673_amd import stafem
+    return stafem
+
+
+def _hip():
+    lib = ctypes.CDLL("libamdhip64.so.7")
+    lib.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    lib.hipMemcpy.restype = ctypes.c_int
+    return lib
+
+
+def test_audit_detects_corrupted_values_and_clears_after_rebuild():
+    Sm = S()
+    w = W.make_fracture(seed=4, n=10, counts=[300, 700, 200])
+    asm = Sm.Assembler.from_workload(w)
+    assert asm.audit() == {"values_differing": 0, "tets_differing": 0}
+    for ids, st in list(w.frames) + W.merge_stream(w.frames)[:2]:
+        asm.apply_edits(*Sm.upload_frame(ids, st))
+    assert asm.audit() == {"values_differing": 0, "tets_differing": 0}
+    # flip one maintained value behind the library's back
+    torch.cuda.synchronize()
+    k = asm.nnz // 3
+    bad = np.array([12345.678], dtype=np.float64)
+    assert _hip().hipMemcpy(asm.values_ptr() + 8 * k, bad.ctypes.data, 8, 1) == 0  # host to device
+    assert asm.audit() == {"values_differing": 1, "tets_differing": 0}
+    asm.full_rebuild()
+    assert asm.audit() == {"values_differing": 0, "tets_differing": 0}
+    # parameters changed: the audit refuses until a rebuild
+    E2 = torch.from_numpy(w.E * 1.5).cuda()
+    asm.set_params(E=E2)
+    with pytest.raises(Sm.StafemError) as ex:
+        asm.audit()
+    assert ex.value.code == Sm.STA_ESTALE
+    asm.full_rebuild()
+    assert asm.audit() == {"values_differing": 0, "tets_differing": 0}
+    asm.close()
+
+
+def test_forced_allocation_failure_reports_enomem_and_leaks_nothing():
+    Sm = S()
+    w = W.make_fracture(seed=5, n=30)
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    try:
+        for k in (1, 9, 20):
+            os.environ["STA_FAIL_ALLOC_AT"] = str(k)
+            with pytest.raises(Sm.StafemError) as ex:
+                Sm.Assembler.from_workload(w)
+            assert ex.value.code == Sm.STA_ENOMEM, k
+            del os.environ["STA_FAIL_ALLOC_AT"]
+            asm = Sm.Assembler.from_workload(w)  # and without the injection the build works
+            asm.close()
+    finally:
+        os.environ.pop("STA_FAIL_ALLOC_AT", None)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    # the 30^3 context holds about 350 MB; three failed builds must not have kept theirs
+    assert free0 - free1 < 64 << 20, (free0 - free1)
+
+
+def test_barrier_probe_reports_positive_costs():
+    d = S().barrier_probe()
+    assert 0 < d["empty_kernel_us"] < d["two_empty_kernels_us"]
+    for g in (8, 32):
+        assert d[f"barrier_kernel_{g}wg_us"] is not None and d[f"barrier_kernel_{g}wg_us"] > 0
+    print("[barrier]", d, flush=True)
