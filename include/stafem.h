@@ -144,8 +144,12 @@ sta_status sta_apply_edits_delta(sta_ctx* ctx, const int32_t* ids_dev, const uin
 sta_status sta_apply_edits_dev(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* states_dev,
                                const int32_t* n_dev, int64_t capacity, void* stream);
 
-/* Device pointer to the nnz CSR values (borrowed; valid until sta_destroy,
- * updated in place; order reads after the producing work on the stream). */
+/* The maintained matrix A_t of Sec. 3.3 (the operator the streaming update
+ * keeps equal to a rebuild from the current mask after every frame of
+ * Alg. 1): device pointer to its nnz CSR values in the pattern of
+ * sta_pattern_ptrs.  Borrowed: valid until sta_destroy and updated in place
+ * by sta_full_rebuild / sta_apply_edits*; order reads after the producing work
+ * on the stream.  NULL for a NULL context. */
 const double* sta_values_ptr(const sta_ctx* ctx);
 
 /* Copy the nnz values into a caller-owned device buffer (stream-ordered). */
@@ -155,12 +159,17 @@ sta_status sta_copy_values(const sta_ctx* ctx, double* dst_dev, void* stream);
 sta_status sta_sizes(const sta_ctx* ctx, int64_t* n_rows, int64_t* nnz, int64_t* n_diag_blocks,
                      int64_t* n_off_blocks);
 
-/* Device pointers to the CSR row pointer (n_rows+1) and column index (nnz)
- * arrays, and to the active mask (n_tets uint8).  Borrowed. */
+/* The fixed superset pattern (Sec. 3.1: every node pair that shares a
+ * candidate tet, whatever the mask) and the active mask a_t of Sec. 3.1:
+ * device pointers to the CSR row pointer (n_rows+1) and column index (nnz)
+ * arrays, and to the mask (n_tets uint8).  Borrowed, valid until
+ * sta_destroy; the pattern never changes, the mask is updated in place by
+ * every frame. */
 sta_status sta_pattern_ptrs(const sta_ctx* ctx, const int32_t** rowptr_dev, const int32_t** colidx_dev,
                             const uint8_t** mask_dev);
 
-/* Copy the CSR pattern to host arrays of n_rows+1 and nnz int32.  Synchronous. */
+/* The same superset pattern copied to host arrays of n_rows+1 and nnz int32.
+ * Synchronous. */
 sta_status sta_pattern_host(const sta_ctx* ctx, int32_t* rowptr, int32_t* colidx);
 
 /* Statistics of the last sta_apply_edits, written to out[0 .. n_out-1]:
