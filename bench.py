@@ -962,7 +962,7 @@ def face_pair_count(tets):
 
 
 # Connectivity is rebuilt from the mask periodically (paper Sec. 3.6), with no period given:
-# here once per 4 frames, the frames per scenario of the paper's elasticity study (Sec. 5).
+# here once per 4 frames, the frames per scenario of the paper's elasticity study (Sec. 5.2).
 CONNECTIVITY_PERIOD = 4
 
 
@@ -1141,7 +1141,7 @@ def main():
                     help="force fused,rebuild_qd,rebuild_qo,stream_qd,stream_qo,grid_cap,rebuild_nt (skips tuning)")
     ap.add_argument("--cpu-sample", type=int, default=48, help="oracle rebuilds in the CPU baseline sample")
     ap.add_argument("--quick", action="store_true",
-                    help="headline timed steps, 3 rebuilds and a 256 MiB reference copy only (for profiler runs)")
+                    help="headline timed steps, 3 rebuilds and a 512 MiB reference copy only (for profiler runs)")
     ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
                     help="file for the full report (per-frame rows, autotuner report, every section)")
     args = ap.parse_args()
@@ -1205,8 +1205,9 @@ def main():
     if args.quick:
         for _ in range(3):
             asm.full_rebuild()
-        # reference copy of known size (256 MiB read + 256 MiB written) for counter scaling
-        src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
+        # reference copy of known size (512 MiB read + 512 MiB written, larger than any other
+        # copy the bench makes) for counter scaling
+        src = torch.ones(1 << 26, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
