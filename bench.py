@@ -139,11 +139,17 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a, dtype=np.float64), q))
 
 
+# Host-only sources (argument checks, sequencing, tuning): no kernel and no data layout.
+HOST_ONLY_SOURCES = ("api.hip", "batch.hip")
+
+
 def source_sha():
-    """Digest of every kernel source: counter records taken with other sources are not used."""
+    """Digest of the sources that decide what the kernels read and write (every kernel file,
+    the internal header and the host pattern builder): counter records taken with other
+    sources are not used."""
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".h", ".cpp")):
+        if name.endswith((".hip", ".h", ".cpp")) and name not in HOST_ONLY_SOURCES:
             with open(os.path.join(CSRC, name), "rb") as f:
                 h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
