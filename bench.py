@@ -42,7 +42,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "per-frame A_t update us + touched slots/s, streaming vs GPU rebuild; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-CSRC = os.path.join(ROOT, "paper_2605_11673_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -139,20 +138,28 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a, dtype=np.float64), q))
 
 
-# Host-only sources (argument checks, sequencing, tuning): no kernel and no data layout.
-HOST_ONLY_SOURCES = ("api.hip", "batch.hip")
+LIB = os.path.join(ROOT, "paper_2605_11673_amd", "libstafem.so")
 
 
 def source_sha():
-    """Digest of the sources that decide what the kernels read and write (every kernel file,
-    the internal header and the host pattern builder): counter records taken with other
-    sources are not used."""
-    h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".h", ".cpp")) and name not in HOST_ONLY_SOURCES:
-            with open(os.path.join(CSRC, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
-    return h.hexdigest()[:16]
+    """Digest of the library's device code (its .hip_fatbin section): counter records taken
+    with other kernels are not used.  The device code is rebuilt bit for bit from the same
+    kernel sources, and host-only changes leave it alone."""
+    import struct
+
+    try:
+        with open(LIB, "rb") as f:
+            data = f.read()
+    except OSError:
+        return None
+    shoff = struct.unpack_from("<Q", data, 0x28)[0]
+    shentsize, shnum, shstrndx = struct.unpack_from("<HHH", data, 0x3A)
+    secs = [struct.unpack_from("<IIQQQQ", data, shoff + i * shentsize) for i in range(shnum)]
+    stroff = secs[shstrndx][4]
+    for name, _typ, _flags, _addr, offset, size in secs:
+        if data[stroff + name:data.index(b"\0", stroff + name)] == b".hip_fatbin":
+            return hashlib.sha256(data[offset:offset + size]).hexdigest()[:16]
+    return None
 
 
 _TRAFFIC = None
@@ -166,7 +173,8 @@ def _traffic():
                 d = json.load(f)
         except (OSError, ValueError):
             d = {}
-        _TRAFFIC = d if d.get("source_sha") == source_sha() else {}
+        sha = source_sha()
+        _TRAFFIC = d if sha is not None and d.get("device_code_sha") == sha else {}
     return _TRAFFIC
 
 

@@ -190,6 +190,14 @@ sta_status sta_last_frame_stats(sta_ctx* ctx, void* stream, int64_t* out, int n_
  * sta_kernel_times synchronises `stream`, writes per kernel id the number of
  * launches and their summed event-to-event duration in milliseconds (arrays
  * of STA_NUM_KERNELS), and resets the counters. */
+/* Per-call trace: when the environment variable STA_TRACE names a file at
+ * context build, every sta_full_rebuild and sta_apply_edits* call on the
+ * context appends one JSON line to it (a sequence number, the call, its edit
+ * count or capacity, the frame mode and the host time since the build, in
+ * microseconds), flushed at once.  With STA_TRACE_STATS=1 as well, each frame
+ * call synchronises its stream and adds the frame's statistics (the nine
+ * values of sta_last_frame_stats).  The file is closed by sta_destroy.  A
+ * file that cannot be opened for appending fails the build with STA_EINVAL. */
 #define STA_KERNEL_ELEMENT 0   /* element contributions (rebuild / activation) */
 #define STA_KERNEL_REDUCE 1    /* re-sum of every block (rebuild) */
 #define STA_KERNEL_EDITS 2     /* streaming phase 1: validate, flip, claim */

@@ -2,6 +2,7 @@
 // device allocation, the host pattern hand-off and kernel sequencing.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -147,6 +148,11 @@ hipError_t timed(sta_ctx* c, int kernel, hipStream_t s, F&& launch, bool single 
     }
     c->timed.push_back({kernel, a, b});
     return e;
+}
+
+double host_seconds()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
 }  // namespace
@@ -360,6 +366,18 @@ sta_status build_context(const double* x, int64_t n_nodes, const int32_t* tets, 
         delete c;
         return fail(nullptr, STA_EDEGENERATE, "a candidate tet has zero volume (det == 0)");
     }
+    const char* tp = std::getenv("STA_TRACE");
+    if (tp && *tp) {
+        c->trace = std::fopen(tp, "a");
+        if (!c->trace) {
+            free_all(c);
+            delete c;
+            return fail(nullptr, STA_EINVAL, std::string("STA_TRACE: cannot open ") + tp + " for appending");
+        }
+        const char* ts = std::getenv("STA_TRACE_STATS");
+        c->trace_stats = ts && std::atoi(ts) != 0;
+        c->trace_t0 = host_seconds();
+    }
     c->node_off = node_off;
     c->tet_off = tet_off;
     c->nnz_off.resize(node_off.size());
@@ -372,6 +390,31 @@ sta_status build_context(const double* x, int64_t n_nodes, const int32_t* tets, 
 }  // namespace sta
 
 namespace {
+
+// One JSON line per traced call (after the call's launches are queued).  With
+// trace_stats the stream is synchronised and the frame's statistics added.
+void trace_call(sta_ctx* ctx, const char* call, int64_t n, bool n_is_capacity, hipStream_t s)
+{
+    if (!ctx->trace)
+        return;
+    const char* mode = ctx->fused ? "one launch" : "two launches";
+    std::fprintf(ctx->trace, "{\"seq\": %lld, \"call\": \"%s\", \"%s\": %lld, \"frame_mode\": \"%s\", "
+                 "\"host_us\": %.1f",
+                 (long long)ctx->trace_seq++, call, n_is_capacity ? "capacity" : "edits", (long long)n, mode,
+                 (host_seconds() - ctx->trace_t0) * 1e6);
+    if (ctx->trace_stats && std::strncmp(call, "apply_edits", 11) == 0) {
+        int64_t st[STA_NUM_FRAME_STATS] = {0};
+        if (sta_last_frame_stats(ctx, s, st, STA_NUM_FRAME_STATS) == STA_OK)
+            std::fprintf(ctx->trace,
+                         ", \"stats\": {\"diag_blocks\": %lld, \"off_blocks\": %lld, \"diag_incidences\": %lld, "
+                         "\"off_incidences\": %lld, \"touched_slots\": %lld, \"changed\": %lld, "
+                         "\"activated\": %lld, \"edits\": %lld, \"rolled_back\": %lld}",
+                         (long long)st[0], (long long)st[1], (long long)st[2], (long long)st[3], (long long)st[4],
+                         (long long)st[5], (long long)st[6], (long long)st[7], (long long)st[8]);
+    }
+    std::fprintf(ctx->trace, "}\n");
+    std::fflush(ctx->trace);
+}
 
 // One frame: two launches, or one persistent launch.
 sta_status run_frame(sta_ctx* ctx, const int32_t* ids, const uint8_t* states, int32_t n_host, const int32_t* n_dev,
@@ -446,6 +489,7 @@ sta_status sta_full_rebuild(sta_ctx* ctx, void* stream)
     if (e != hipSuccess)
         return hip_fail(ctx, e, "full_rebuild launch");
     ctx->stale = false;
+    trace_call(ctx, "full_rebuild", 0, false, s);
     return STA_OK;
 }
 
@@ -460,7 +504,11 @@ sta_status sta_apply_edits(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* 
         return fail(ctx, STA_EINVAL, "NULL edit array");
     if (ctx->stale)
         return fail(ctx, STA_ESTALE, "parameters changed: call sta_full_rebuild before sta_apply_edits");
-    return run_frame(ctx, ids_dev, states_dev, (int32_t)n_edits, nullptr, static_cast<hipStream_t>(stream));
+    const sta_status st = run_frame(ctx, ids_dev, states_dev, (int32_t)n_edits, nullptr,
+                                    static_cast<hipStream_t>(stream));
+    if (st == STA_OK)
+        trace_call(ctx, "apply_edits", n_edits, false, static_cast<hipStream_t>(stream));
+    return st;
 }
 
 sta_status sta_apply_edits_dev(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* states_dev, const int32_t* n_dev,
@@ -474,7 +522,11 @@ sta_status sta_apply_edits_dev(sta_ctx* ctx, const int32_t* ids_dev, const uint8
         return fail(ctx, STA_EINVAL, "NULL edit array or count");
     if (ctx->stale)
         return fail(ctx, STA_ESTALE, "parameters changed: call sta_full_rebuild before sta_apply_edits_dev");
-    return run_frame(ctx, ids_dev, states_dev, (int32_t)capacity, n_dev, static_cast<hipStream_t>(stream));
+    const sta_status st = run_frame(ctx, ids_dev, states_dev, (int32_t)capacity, n_dev,
+                                    static_cast<hipStream_t>(stream));
+    if (st == STA_OK)
+        trace_call(ctx, "apply_edits_dev", capacity, true, static_cast<hipStream_t>(stream));
+    return st;
 }
 
 sta_status sta_apply_edits_delta(sta_ctx* ctx, const int32_t* ids_dev, const uint8_t* states_dev, int64_t n_edits,
@@ -492,7 +544,10 @@ sta_status sta_apply_edits_delta(sta_ctx* ctx, const int32_t* ids_dev, const uin
     const hipError_t e = timed(ctx, STA_KERNEL_DELTA, s, [&] {
         return launch_delta_frame(ctx->v, ids_dev, states_dev, (int32_t)n_edits, n_dev, s);
     });
-    return e == hipSuccess ? STA_OK : hip_fail(ctx, e, "delta frame");
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "delta frame");
+    trace_call(ctx, "apply_edits_delta", n_edits, n_dev != nullptr, s);
+    return STA_OK;
 }
 
 const double* sta_values_ptr(const sta_ctx* ctx)
@@ -950,6 +1005,8 @@ void sta_destroy(sta_ctx* ctx)
         (void)hipHostFree(ctx->cg_host);
     if (ctx->cc_host)
         (void)hipHostFree(ctx->cc_host);
+    if (ctx->trace)
+        std::fclose(ctx->trace);
     free_all(ctx);
     delete ctx;
 }

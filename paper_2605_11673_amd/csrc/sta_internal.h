@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <cstdio>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -247,6 +248,11 @@ struct sta_ctx {
     int frame_max_grid = 0; // co-resident workgroups for the fused kernel (per stream_map)
     unsigned barrier_spin = sta::kBarrierSpinDefault;  // polls before the fused frame's barrier gives up
     bool fused_used = false;  // a fused frame ran since the last rebuild (stamps may be left taken)
+    // per-call trace (environment variable STA_TRACE names a JSON-lines file)
+    FILE* trace = nullptr;
+    bool trace_stats = false;  // STA_TRACE_STATS=1: synchronise and add each frame's statistics
+    int64_t trace_seq = 0;
+    double trace_t0 = 0.0;     // host seconds at context build
     // lazily allocated workspaces
     double* cg_ws = nullptr;        // 7 vectors of n_rows (two copies of p) + partials
     int32_t* cg_dpos = nullptr;

@@ -80,3 +80,47 @@ def test_barrier_probe_reports_positive_costs():
     for g in (8, 32):
         assert d[f"barrier_kernel_{g}wg_us"] is not None and d[f"barrier_kernel_{g}wg_us"] > 0
     print("[barrier]", d, flush=True)
+
+
+def test_trace_writes_one_line_per_call_with_frame_stats(tmp_path):
+    """STA_TRACE names a file at build: every rebuild and frame call appends one JSON line;
+    STA_TRACE_STATS=1 adds the frame's statistics, equal to what the stats call returns."""
+    import json
+
+    Sm = S()
+    w = W.make_fracture(seed=6, n=10, counts=[50, 400, 120])
+    path = tmp_path / "trace.jsonl"
+    os.environ["STA_TRACE"] = str(path)
+    os.environ["STA_TRACE_STATS"] = "1"
+    try:
+        asm = Sm.Assembler.from_workload(w)
+    finally:
+        os.environ.pop("STA_TRACE")
+        os.environ.pop("STA_TRACE_STATS")
+    want = []
+    for ids, st in w.frames:
+        asm.apply_edits(*Sm.upload_frame(ids, st))
+        d = asm.last_frame_stats()
+        want.append({k: d[k] for k in Sm.Assembler.FRAME_STATS})
+    asm.full_rebuild()
+    asm.close()
+    lines = [json.loads(l) for l in path.read_text().splitlines()]
+    assert [l["seq"] for l in lines] == list(range(len(w.frames) + 1))
+    assert [l["call"] for l in lines] == ["apply_edits"] * len(w.frames) + ["full_rebuild"]
+    for l, (ids, _), s in zip(lines, w.frames, want):
+        assert l["edits"] == len(ids) and l["stats"] == s and l["stats"]["edits"] == len(ids)
+    assert "stats" not in lines[-1]
+    assert all(a["host_us"] <= b["host_us"] for a, b in zip(lines, lines[1:]))
+    # a context built without STA_TRACE writes nothing more
+    asm = Sm.Assembler.from_workload(w)
+    asm.apply_edits(*Sm.upload_frame(*w.frames[0]))
+    asm.close()
+    assert len(path.read_text().splitlines()) == len(lines)
+    # an unopenable trace file fails the build
+    os.environ["STA_TRACE"] = str(tmp_path / "no_such_dir" / "t.jsonl")
+    try:
+        with pytest.raises(Sm.StafemError) as ex:
+            Sm.Assembler.from_workload(w)
+        assert ex.value.code == Sm.STA_EINVAL
+    finally:
+        os.environ.pop("STA_TRACE")
