@@ -102,13 +102,26 @@ __device__ __forceinline__ void gather_block(const DevView& v, const double* __r
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_adjoint_element(DevView v, const double* __restrict__ gA,
+// The element pass's dynamic LDS, reserved and unused: it caps the pass at two
+// workgroups per CU.  More resident waves gather more cotangent rows at once
+// than the caches hold (on the 384k-tet fracture state: 81 us at two
+// workgroups per CU, 86 us at three, 97 us at four).
+constexpr size_t kAdjointReservedLds = 56 << 10;
+
+__global__ __launch_bounds__(kBlock) void k_adjoint_element(DevView v, const int32_t* __restrict__ order,
+                                                            int32_t n_chunks, const double* __restrict__ gA,
                                                             double* __restrict__ g_logE, double* __restrict__ xbar)
 {
-    // each XCD takes one contiguous eighth of the tets: neighbouring tets share
-    // node blocks, so their cotangent rows stay in one L2 (132 -> 85 us on the
-    // 384k-tet fracture state, same bits)
-    const int e = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    // each XCD takes one contiguous share of the chunk order, chunks that are
+    // near in space: neighbouring tets share node blocks, so their cotangent
+    // rows stay in one L2 (132 -> 85 us for contiguous eighths of the tet ids
+    // on the 384k-tet fracture state; 81 -> 79 us for the Morton chunk order
+    // over the id order, both at two workgroups per CU; same bits throughout)
+    constexpr int kPer = kBlock / kAdjointChunk;
+    const int slot = xcd_remap(blockIdx.x, gridDim.x) * kPer + threadIdx.x / kAdjointChunk;
+    if (slot >= n_chunks)
+        return;
+    const int e = order[slot] * kAdjointChunk + (threadIdx.x % kAdjointChunk);
     if (e >= v.n_tets)
         return;
     const int* pos = v.e2p + 10 * (size_t)e;
@@ -299,12 +312,14 @@ __global__ __launch_bounds__(kBlock) void k_slot_outer(int n_rows, const int32_t
 
 }  // namespace
 
-hipError_t launch_adjoint(const DevView& v, const double* gA, double* g_logE, double* g_x, double* xbar,
-                          hipStream_t s)
+hipError_t launch_adjoint(const DevView& v, const int32_t* order, int32_t n_chunks, const double* gA, double* g_logE,
+                          double* g_x, double* xbar, hipStream_t s)
 {
+    // kBlock / kAdjointChunk chunks per workgroup, so the grid covers n_chunks
+    const unsigned grid = (unsigned)((n_chunks + kBlock / kAdjointChunk - 1) / (kBlock / kAdjointChunk));
     if (v.n_tets > 0)
-        hipLaunchKernelGGL(k_adjoint_element, dim3((v.n_tets + kBlock - 1) / kBlock), dim3(kBlock), 0, s, v, gA,
-                           g_logE, xbar);
+        hipLaunchKernelGGL(k_adjoint_element, dim3(grid), dim3(kBlock), kAdjointReservedLds, s, v, order, n_chunks,
+                           gA, g_logE, xbar);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || v.n_nodes == 0)
         return e;
@@ -393,7 +408,8 @@ extern "C" sta_status sta_adjoint_noalloc(sta_ctx* ctx, const double* gA_dev, do
     }
     // every diagonal incidence's three entries are written by the element pass
     // before the node pass reads them, so nothing needs clearing
-    e = sta::launch_adjoint(ctx->v, gA_dev, g_logE_dev, g_x_dev, xbar, static_cast<hipStream_t>(stream));
+    e = sta::launch_adjoint(ctx->v, ctx->adj_order, ctx->adj_chunks, gA_dev, g_logE_dev, g_x_dev, xbar,
+                            static_cast<hipStream_t>(stream));
     if (e != hipSuccess) {
         ctx->errmsg = std::string("sta_adjoint_noalloc launch: ") + hipGetErrorString(e);
         return STA_EHIP;

@@ -2,11 +2,14 @@
 // device allocation, the host pattern hand-off and kernel sequencing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <utility>
+#include <vector>
 
 #include "sta_internal.h"
 
@@ -170,6 +173,70 @@ std::string& build_error()
     return g_build_err;
 }
 
+// Spread the low 10 bits of v to every third bit (Morton interleave).
+static uint64_t spread3(uint32_t v)
+{
+    uint64_t x = v & 0x3ffu;
+    x = (x | (x << 16)) & 0x030000ffull;
+    x = (x | (x << 8)) & 0x0300f00full;
+    x = (x | (x << 4)) & 0x030c30c3ull;
+    x = (x | (x << 2)) & 0x09249249ull;
+    return x;
+}
+
+// The adjoint's chunk order: chunks of kAdjointChunk consecutive tet ids,
+// sorted by (mesh of the chunk's first tet, Morton code of the chunk's
+// centroid on a 1024^3 grid over that mesh's bounding box), ties by chunk id.
+// x: n_nodes * 3 row-major; node_off / tet_off: the meshes' node and tet ranges.
+static std::vector<int32_t> adjoint_chunk_order(const double* x, const std::vector<int4>& T,
+                                                const std::vector<int64_t>& node_off,
+                                                const std::vector<int64_t>& tet_off)
+{
+    const int64_t n_tets = (int64_t)T.size();
+    const int64_t nc = (n_tets + kAdjointChunk - 1) / kAdjointChunk;
+    const size_t n_mesh = tet_off.size() > 1 ? tet_off.size() - 1 : 0;
+    std::vector<double> lo(3 * n_mesh, 0.0), span(3 * n_mesh, 0.0);
+    for (size_t m = 0; m < n_mesh; ++m) {
+        double l[3] = {INFINITY, INFINITY, INFINITY}, h[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int64_t i = node_off[m]; i < node_off[m + 1]; ++i)
+            for (int k = 0; k < 3; ++k) {
+                l[k] = std::min(l[k], x[3 * i + k]);
+                h[k] = std::max(h[k], x[3 * i + k]);
+            }
+        for (int k = 0; k < 3; ++k) {
+            lo[3 * m + k] = std::isfinite(l[k]) ? l[k] : 0.0;
+            span[3 * m + k] = h[k] > l[k] ? h[k] - l[k] : 0.0;
+        }
+    }
+    std::vector<std::pair<uint64_t, int32_t>> key((size_t)nc);
+    size_t m = 0;
+    for (int64_t c = 0; c < nc; ++c) {
+        const int64_t e0 = c * kAdjointChunk, e1 = std::min(n_tets, e0 + kAdjointChunk);
+        while (m + 1 < n_mesh && tet_off[m + 1] <= e0)
+            ++m;
+        double s[3] = {0.0, 0.0, 0.0};
+        for (int64_t e = e0; e < e1; ++e) {
+            const int id[4] = {T[e].x, T[e].y, T[e].z, T[e].w};
+            for (int a = 0; a < 4; ++a)
+                for (int k = 0; k < 3; ++k)
+                    s[k] += x[3 * (int64_t)id[a] + k];
+        }
+        uint64_t code = 0;
+        for (int k = 0; k < 3 && n_mesh > 0; ++k) {
+            const double sp = span[3 * m + k];
+            const double t = sp > 0.0 ? (s[k] / (4.0 * (double)(e1 - e0)) - lo[3 * m + k]) / sp : 0.0;
+            const uint32_t q = (uint32_t)std::min(1023.0, std::max(0.0, std::floor(t * 1024.0)));
+            code |= spread3(q) << k;
+        }
+        key[(size_t)c] = {((uint64_t)m << 30) | code, (int32_t)c};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int32_t> order((size_t)nc);
+    for (int64_t c = 0; c < nc; ++c)
+        order[(size_t)c] = key[(size_t)c].second;
+    return order;
+}
+
 sta_status build_context(const double* x, int64_t n_nodes, const int32_t* tets, int64_t n_tets, const double* E,
                          double nu, double rho, double dt, const uint8_t* mask0, void* stream,
                          const std::vector<int64_t>& node_off, const std::vector<int64_t>& tet_off, sta_ctx** out)
@@ -269,6 +336,8 @@ sta_status build_context(const double* x, int64_t n_nodes, const int32_t* tets, 
     ALLOC(c->dinc, 4 * n_tets);
     TetRecord* trec = nullptr;
     ALLOC(trec, n_tets);
+    const int64_t n_chunks = (n_tets + kAdjointChunk - 1) / kAdjointChunk;
+    ALLOC(c->adj_order, n_chunks);
 #undef ALLOC
     if (e != hipSuccess) {
         free_all(c);
@@ -308,6 +377,9 @@ sta_status build_context(const double* x, int64_t n_nodes, const int32_t* tets, 
     if (e == hipSuccess) e = upload(e2b, he2b.data(), he2b.size(), s);
     if (e == hipSuccess) e = upload(e2p, P.e2p.data(), P.e2p.size(), s);
     if (e == hipSuccess) e = upload(c->dinc, P.dinc.data(), P.dinc.size(), s);
+    const std::vector<int32_t> order = adjoint_chunk_order(x, hT, node_off, tet_off);
+    if (e == hipSuccess) e = upload(c->adj_order, order.data(), order.size(), s);
+    c->adj_chunks = (int32_t)n_chunks;
     {
         std::vector<TetRecord> hr((size_t)n_tets);
         for (int64_t t = 0; t < n_tets; ++t) {
@@ -891,7 +963,10 @@ sta_status sta_adjoint(sta_ctx* ctx, const double* gA_dev, double* g_logE_dev, d
         return fail(ctx, STA_ENOMEM, "adjoint workspace allocation failed");
     hipStream_t s = static_cast<hipStream_t>(stream);
     e = timed(ctx, STA_KERNEL_ADJOINT, s,
-              [&] { return launch_adjoint(ctx->v, gA_dev, g_logE_dev, g_x_dev, ctx->adj_xbar, s); });
+              [&] {
+                  return launch_adjoint(ctx->v, ctx->adj_order, ctx->adj_chunks, gA_dev, g_logE_dev, g_x_dev,
+                                        ctx->adj_xbar, s);
+              });
     if (e != hipSuccess)
         return hip_fail(ctx, e, "adjoint launch");
     return STA_OK;

@@ -259,6 +259,8 @@ struct sta_ctx {
     sta::CgScalars* cg_s = nullptr;
     sta::CgScalars* cg_host = nullptr;  // pinned
     double* adj_xbar = nullptr;     // 3 doubles per diagonal incidence
+    int32_t* adj_order = nullptr;   // adjoint visiting order of the kAdjointChunk-tet chunks
+    int32_t adj_chunks = 0;
     int32_t* dinc = nullptr;        // per diagonal incidence: its tet (segments in ascending tet id)
     double* tet_ml = nullptr;       // per tet: lumped mass per vertex dof, (rho V) / 4
     bool tet_ml_stale = true;
@@ -337,8 +339,13 @@ hipError_t launch_set_params(const DevView& v, const double* x_aos, const double
 hipError_t launch_refresh_records(const DevView& v, TetRecord* trec, hipStream_t s);
 
 // Adjoint and CG launchers (adjoint.hip, cg.hip).
-hipError_t launch_adjoint(const DevView& v, const double* gA, double* g_logE, double* g_x, double* xbar,
-                          hipStream_t s);
+// The adjoint visits the tets in chunks of kAdjointChunk consecutive ids, in
+// an order fixed at context build (each mesh's chunks by the Morton code of
+// their centroid), so that the chunks in flight together are near in space
+// and their cotangent rows shared in cache.  Any order gives the same bits.
+constexpr int kAdjointChunk = 16;
+hipError_t launch_adjoint(const DevView& v, const int32_t* order, int32_t n_chunks, const double* gA, double* g_logE,
+                          double* g_x, double* xbar, hipStream_t s);
 hipError_t launch_slot_outer(int n_rows, const int32_t* rowptr, const int32_t* colidx, const double* a,
                              const double* b, double alpha, double* out, hipStream_t s);
 hipError_t launch_diag_positions(const DevView& v, int32_t* dpos, hipStream_t s);
