@@ -22,7 +22,11 @@
 // Each pass is its own launch: within a pass, loads may see another XCD's
 // stale copy of a pointer, which only delays convergence (every update is a
 // monotone atomic minimum); the launch boundary makes all updates visible to
-// the next pass.  The host checks a change flag after each hooking pass.
+// the next pass.  Passes are queued a few at a time, each returning at once
+// unless the pass before it changed something; after the batch the labels
+// (each climbing to its root) and the component count follow, and the host
+// reads the flags and the count back once.  If the batch's last pass still
+// changed something, another batch follows.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,7 +45,23 @@ unsigned blocks(int64_t n)
     return (unsigned)((n + kBlock - 1) / kBlock);
 }
 
-// flag[0]: changed in this pass; flag[1]: number of components
+// Hooking passes per batch: the vertex rebuild mostly converges in two, the
+// face rebuild in three (on the 384k-tet fracture stream: vertex 77 / 78 / 81
+// / 91 us per rebuild at 2 / 3 / 4 / 6 passes per batch, face 147 / 117 /
+// 122 / 126 us).  Flag words: [0, batch) set by hooking pass p when it
+// changes a pointer; kMaxBatch: a climb of the labelling pass stopped short
+// of a root; kMaxBatch + 1: the number of components.
+constexpr int kVertexBatch = 2, kFaceBatch = 3;
+constexpr int kMaxBatch = 3;
+constexpr int kTruncWord = kMaxBatch, kCountWord = kMaxBatch + 1;
+constexpr int kFlagWords = kMaxBatch + 2;
+
+// Pass p > 0 of a batch runs only if pass p - 1 changed something (gate
+// NULL: always).  The word is the same for every thread of the launch.
+__device__ __forceinline__ bool gated_off(const uint32_t* gate)
+{
+    return gate && *gate == 0u;
+}
 
 // Seed (replaces the identity start): every vertex points at the smallest
 // vertex of its active tets, or at itself if that is smaller or it has none,
@@ -50,12 +70,15 @@ unsigned blocks(int64_t n)
 // and only decreases, as every later update does; the hooking passes then
 // start from local minima and contend far less on their atomics.
 __global__ __launch_bounds__(kBlock) void k_cc_seed(DevView v, const int32_t* __restrict__ dinc, int* f,
-                                                    uint32_t* mark)
+                                                    uint32_t* mark, uint32_t* flag)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < kFlagWords)
+        flag[i] = 0u;  // the first batch's flags
     if (i >= v.n_nodes)
         return;
     int m = i;
+    bool any = false;
     const int b = v.ndiag[i];
     if (b >= 0) {
         const BlockDesc d = v.desc[b];
@@ -75,11 +98,12 @@ __global__ __launch_bounds__(kBlock) void k_cc_seed(DevView v, const int32_t* __
                     const int4 t = v.T[e[j]];
                     const int lo = min(min(t.x, t.y), min(t.z, t.w));
                     m = lo < m ? lo : m;
+                    any = true;
                 }
         }
     }
     f[i] = m;
-    mark[i] = 0u;
+    mark[i] = any ? 1u : 0u;  // a vertex of an active tet
 }
 
 // Follow parent pointers from x towards its root (at most kMaxSteps hops:
@@ -99,10 +123,10 @@ __device__ __forceinline__ int climb(const int* f, int x)
 
 // Hooking pass: each active tet lowers the roots of its four vertices (and
 // the vertices themselves) to the smallest of those roots.
-__global__ __launch_bounds__(kBlock) void k_cc_hook(DevView v, int* f, uint32_t* flag)
+__global__ __launch_bounds__(kBlock) void k_cc_hook(DevView v, int* f, const uint32_t* gate, uint32_t* changed_out)
 {
     const int e = blockIdx.x * kBlock + threadIdx.x;
-    if (e >= v.n_tets || !v.mask[e])
+    if (gated_off(gate) || e >= v.n_tets || !v.mask[e])
         return;
     const int4 t = v.T[e];
     const int x[4] = {t.x, t.y, t.z, t.w};
@@ -121,64 +145,58 @@ __global__ __launch_bounds__(kBlock) void k_cc_hook(DevView v, int* f, uint32_t*
         }
     }
     if (changed)
-        flag[0] = 1u;
+        changed_out[0] = 1u;
 }
 
 // Shortcut pass: every pointer to the root it reaches (only thread i writes f[i]).
-__global__ __launch_bounds__(kBlock) void k_cc_shortcut(int n_nodes, int* f, uint32_t* flag)
+__global__ __launch_bounds__(kBlock) void k_cc_shortcut(int n, int* f, const uint32_t* gate)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n_nodes)
+    if (gated_off(gate) || i >= n)
         return;
     const int p = f[i];
     const int r = climb(f, p);
-    if (r < p) {
+    if (r < p)
         f[i] = r;
-        flag[0] = 1u;
-    }
 }
 
-// Label every tet with its component's root (-1 if inactive) and mark the
-// vertices of active tets (plain stores: many tets share a vertex).
-__global__ __launch_bounds__(kBlock) void k_cc_label(DevView v, const int* __restrict__ f,
-                                                     int32_t* __restrict__ label, uint32_t* mark)
-{
-    const int e = blockIdx.x * kBlock + threadIdx.x;
-    if (e >= v.n_tets)
-        return;
-    int32_t l = -1;
-    if (v.mask[e]) {
-        const int4 t = v.T[e];
-        l = f[t.x];
-        mark[t.x] = 1u;
-        mark[t.y] = 1u;
-        mark[t.z] = 1u;
-        mark[t.w] = 1u;
-    }
-    label[e] = l;
-}
-
-// Components = marked vertices that are their own root (each component's
-// root is its smallest vertex, which belongs to an active tet).
-__global__ __launch_bounds__(kBlock) void k_cc_count(int n_nodes, const int* __restrict__ f,
-                                                     const uint32_t* __restrict__ mark, uint32_t* flag)
+// After the hooking passes have converged (roots fixed): thread e < n_tets
+// labels tet e with the root of its first vertex (-1 if inactive), climbing
+// there itself; thread i < n_nodes counts vertex i if it is a root and a
+// vertex of an active tet (each component's root is its smallest vertex,
+// which belongs to an active tet).  A climb that stops at the step limit
+// leaves a non-root, reported in *truncated (then another batch follows).
+__global__ __launch_bounds__(kBlock) void k_cc_finish(DevView v, const int* __restrict__ f,
+                                                      const uint32_t* __restrict__ mark, int32_t* __restrict__ label,
+                                                      uint32_t* count, uint32_t* truncated)
 {
     __shared__ uint32_t s_count;
     if (threadIdx.x == 0)
         s_count = 0u;
     __syncthreads();
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n_nodes && mark[i] && f[i] == i)
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < v.n_tets) {
+        int32_t l = -1;
+        if (v.mask[t]) {
+            l = climb(f, v.T[t].x);
+            if (f[l] != l)
+                truncated[0] = 1u;
+        }
+        label[t] = l;
+    }
+    if (t < v.n_nodes && mark[t] && f[t] == t)
         atomicAdd(&s_count, 1u);
     __syncthreads();
     if (threadIdx.x == 0 && s_count)
-        atomicAdd(flag + 1, s_count);
+        atomicAdd(count, s_count);
 }
 
 // Face adjacency: parent pointers over tets, each starting at itself.
-__global__ __launch_bounds__(kBlock) void k_ccf_init(int n_tets, int* f)
+__global__ __launch_bounds__(kBlock) void k_ccf_init(int n_tets, int* f, uint32_t* flag)
 {
     const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e < kFlagWords)
+        flag[e] = 0u;  // the first batch's flags
     if (e < n_tets)
         f[e] = e;
 }
@@ -203,10 +221,11 @@ __global__ __launch_bounds__(kBlock) void k_ccf_seed(const uint8_t* __restrict__
 
 // Hooking pass over the face pairs whose two tets are both active.
 __global__ __launch_bounds__(kBlock) void k_ccf_hook(const uint8_t* __restrict__ mask, const int2* __restrict__ pairs,
-                                                     int64_t n_pairs, int* f, uint32_t* flag)
+                                                     int64_t n_pairs, int* f, const uint32_t* gate,
+                                                     uint32_t* changed_out)
 {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= n_pairs)
+    if (gated_off(gate) || k >= n_pairs)
         return;
     const int2 p = pairs[k];
     if (!mask[p.x] || !mask[p.y])
@@ -219,13 +238,15 @@ __global__ __launch_bounds__(kBlock) void k_ccf_hook(const uint8_t* __restrict__
     changed |= atomicMin(f + p.x, lo) > lo;
     changed |= atomicMin(f + p.y, lo) > lo;
     if (changed)
-        flag[0] = 1u;
+        changed_out[0] = 1u;
 }
 
-// Label every tet with its root (-1 if inactive); count the active roots.
+// After the hooking passes have converged: label every tet with its root
+// (-1 if inactive), climbing there itself; count the active roots; report a
+// climb stopped at the step limit in *truncated.
 __global__ __launch_bounds__(kBlock) void k_ccf_label(int n_tets, const uint8_t* __restrict__ mask,
                                                       const int* __restrict__ f, int32_t* __restrict__ label,
-                                                      uint32_t* flag)
+                                                      uint32_t* count, uint32_t* truncated)
 {
     __shared__ uint32_t s_count;
     if (threadIdx.x == 0)
@@ -234,14 +255,16 @@ __global__ __launch_bounds__(kBlock) void k_ccf_label(int n_tets, const uint8_t*
     const int e = blockIdx.x * kBlock + threadIdx.x;
     if (e < n_tets) {
         const bool on = mask[e] != 0;
-        const int r = f[e];
-        label[e] = on ? r : -1;
+        const int r = on ? climb(f, e) : -1;
+        if (on && f[r] != r)
+            truncated[0] = 1u;
+        label[e] = r;
         if (on && r == e)
             atomicAdd(&s_count, 1u);
     }
     __syncthreads();
     if (threadIdx.x == 0 && s_count)
-        atomicAdd(flag + 1, s_count);
+        atomicAdd(count, s_count);
 }
 
 }  // namespace
@@ -290,122 +313,116 @@ std::vector<int2> host_face_pairs(const std::vector<int4>& T)
     return pairs;
 }
 
+// One read-back per batch: the flags and the component count; *passes
+// counts the hooking passes that ran.  converged: the batch's last pass
+// changed nothing and no labelling climb stopped short.
+static hipError_t finish_batch(uint32_t* flag, uint32_t* host, int batch, int* passes, bool& converged,
+                               hipStream_t s)
+{
+    hipError_t e = hipMemcpyAsync(host, flag, sizeof(uint32_t) * kFlagWords, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return e;
+    int ran = 1;
+    for (int p = 0; p + 1 < batch; ++p)
+        ran += host[p] != 0u;
+    *passes += ran;
+    converged = host[batch - 1] == 0u && host[kTruncWord] == 0u;
+    return hipSuccess;
+}
+
 // Face-adjacency labels (smallest tet id of the component, -1 if inactive)
-// into label; *n_components on the host.  f: n_tets ints; synchronises s.
+// into label; *n_components on the host.  f: n_tets ints; flag: kFlagWords
+// words; host_flag: kFlagWords pinned words.  Synchronises s.
 hipError_t run_face_components(const DevView& v, const int2* pairs, int64_t n_pairs, int* f, uint32_t* flag,
                                uint32_t* host_flag, int32_t* label, int64_t* n_components, int* passes,
                                hipStream_t s)
 {
     const unsigned gt = v.n_tets > 0 ? blocks(v.n_tets) : 1u;
-    hipError_t e = hipSuccess;
+    const unsigned gp = n_pairs > 0 ? (unsigned)((n_pairs + kBlock - 1) / kBlock) : 1u;
+    // init also clears the first batch's flags
+    hipLaunchKernelGGL(k_ccf_init, dim3(gt), dim3(kBlock), 0, s, v.n_tets, f, flag);
+    if (n_pairs > 0)
+        hipLaunchKernelGGL(k_ccf_seed, dim3(gp), dim3(kBlock), 0, s, v.mask, pairs, n_pairs, f);
+    hipError_t e = hipGetLastError();
     *passes = 0;
-    if (v.n_tets > 0) {
-        hipLaunchKernelGGL(k_ccf_init, dim3(gt), dim3(kBlock), 0, s, v.n_tets, f);
-        if (n_pairs > 0)
-            hipLaunchKernelGGL(k_ccf_seed, dim3((unsigned)((n_pairs + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                               v.mask, pairs, n_pairs, f);
-        e = hipGetLastError();
-    }
-    for (int phase = 0; phase < 2 && e == hipSuccess; ++phase) {
-        for (int it = 0;; ++it) {
-            if (it > v.n_tets + 2)
-                return hipErrorUnknown;
-            e = hipMemsetAsync(flag, 0, sizeof(uint32_t), s);
-            if (e == hipSuccess && phase == 0 && n_pairs > 0) {
-                hipLaunchKernelGGL(k_ccf_hook, dim3((unsigned)((n_pairs + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                                   v.mask, pairs, n_pairs, f, flag);
-                e = hipGetLastError();
-            }
-            if (e == hipSuccess && v.n_tets > 0) {
-                hipLaunchKernelGGL(k_cc_shortcut, dim3(gt), dim3(kBlock), 0, s, v.n_tets, f, flag + (phase == 0));
-                e = hipGetLastError();
-            }
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(host_flag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess)
-                e = hipStreamSynchronize(s);
-            if (e != hipSuccess)
-                return e;
-            ++*passes;
-            if (*host_flag == 0u)
-                break;
+    // batches of hooking passes until one changes nothing (bounded: every pass
+    // that does not end the loop lowers some pointer; the bound is far above
+    // what a correct pass sequence needs), then the labels, in the same batch
+    for (bool converged = false; e == hipSuccess && !converged;) {
+        if (*passes > v.n_tets + 2)
+            return hipErrorUnknown;
+        if (*passes > 0)
+            e = hipMemsetAsync(flag, 0, sizeof(uint32_t) * kFlagWords, s);
+        for (int p = 0; p < kFaceBatch && e == hipSuccess; ++p) {
+            const uint32_t* gate = p == 0 ? nullptr : flag + p - 1;
+            if (n_pairs > 0)
+                hipLaunchKernelGGL(k_ccf_hook, dim3(gp), dim3(kBlock), 0, s, v.mask, pairs, n_pairs, f, gate,
+                                   flag + p);
+            if (v.n_tets > 0)
+                hipLaunchKernelGGL(k_cc_shortcut, dim3(gt), dim3(kBlock), 0, s, v.n_tets, f, gate);
+            e = hipGetLastError();
         }
+        if (e == hipSuccess && v.n_tets > 0) {
+            hipLaunchKernelGGL(k_ccf_label, dim3(gt), dim3(kBlock), 0, s, v.n_tets, v.mask, f, label,
+                               flag + kCountWord, flag + kTruncWord);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess)
+            e = finish_batch(flag, host_flag, kFaceBatch, passes, converged, s);
     }
     if (e == hipSuccess)
-        e = hipMemsetAsync(flag + 1, 0, sizeof(uint32_t), s);
-    if (e == hipSuccess && v.n_tets > 0) {
-        hipLaunchKernelGGL(k_ccf_label, dim3(gt), dim3(kBlock), 0, s, v.n_tets, v.mask, f, label, flag);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(host_flag, flag + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(s);
-    if (e == hipSuccess)
-        *n_components = *host_flag;
+        *n_components = host_flag[kCountWord];
     return e;
 }
 
 // Component labels into label (device, n_tets); *n_components on the host.
-// Synchronises s.  Returns hipErrorUnknown if the iteration bound is hit.
+// flag: kFlagWords words; host_flag: kFlagWords pinned words.  Synchronises
+// s.  Returns hipErrorUnknown if the iteration bound is hit.
 hipError_t run_components(const DevView& v, const int32_t* dinc, int* f, uint32_t* mark, uint32_t* flag,
                           uint32_t* host_flag, int32_t* label, int64_t* n_components, int* passes, hipStream_t s)
 {
     const unsigned gn = v.n_nodes > 0 ? blocks(v.n_nodes) : 1u;
-    hipLaunchKernelGGL(k_cc_seed, dim3(gn), dim3(kBlock), 0, s, v, dinc, f, mark);
+    const unsigned gt = v.n_tets > 0 ? blocks(v.n_tets) : 1u;
+    const unsigned gf = blocks(std::max(v.n_tets, v.n_nodes) > 0 ? std::max(v.n_tets, v.n_nodes) : 1);
+    // the seed also marks the vertices of active tets and clears the first batch's flags
+    hipLaunchKernelGGL(k_cc_seed, dim3(gn), dim3(kBlock), 0, s, v, dinc, f, mark, flag);
     // one shortcut before the first hooking pass: every vertex climbs its seed
     // chain once, so that the tets' climbs in that pass are short (180 -> 122
     // us per rebuild; the face seeds' chains are short already, and there the
     // extra pass costs more than it saves)
     if (v.n_nodes > 0)
-        hipLaunchKernelGGL(k_cc_shortcut, dim3(gn), dim3(kBlock), 0, s, v.n_nodes, f, flag + 1);
+        hipLaunchKernelGGL(k_cc_shortcut, dim3(gn), dim3(kBlock), 0, s, v.n_nodes, f, nullptr);
     hipError_t e = hipGetLastError();
     *passes = 0;
-    // hooking passes until one changes nothing (then its reads were exact, so
-    // every active tet's vertices share one root), each followed by one
-    // shortcut; then shortcuts until every tree is a star.  Every pass that
-    // does not end its loop lowers some pointer, so the loop is bounded; the
-    // bound below is far above what a correct pass sequence needs.
-    for (int phase = 0; phase < 2 && e == hipSuccess; ++phase) {
-        for (int it = 0;; ++it) {
-            if (it > v.n_nodes + 2)
-                return hipErrorUnknown;
-            e = hipMemsetAsync(flag, 0, sizeof(uint32_t), s);
-            if (e == hipSuccess && phase == 0 && v.n_tets > 0) {
-                hipLaunchKernelGGL(k_cc_hook, dim3(blocks(v.n_tets)), dim3(kBlock), 0, s, v, f, flag);
-                e = hipGetLastError();
-            }
-            if (e == hipSuccess && v.n_nodes > 0) {
-                hipLaunchKernelGGL(k_cc_shortcut, dim3(gn), dim3(kBlock), 0, s, v.n_nodes, f, flag + (phase == 0));
-                e = hipGetLastError();
-            }
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(host_flag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess)
-                e = hipStreamSynchronize(s);
-            if (e != hipSuccess)
-                return e;
-            ++*passes;
-            if (*host_flag == 0u)
-                break;
+    // batches of hooking passes, each followed by a shortcut, until one
+    // changes nothing (then its reads were exact, so every active tet's
+    // vertices share one root); then labels and count in the same batch.
+    // Bounded as in the face variant.
+    for (bool converged = false; e == hipSuccess && !converged;) {
+        if (*passes > v.n_nodes + 2)
+            return hipErrorUnknown;
+        if (*passes > 0)
+            e = hipMemsetAsync(flag, 0, sizeof(uint32_t) * kFlagWords, s);
+        for (int p = 0; p < kVertexBatch && e == hipSuccess; ++p) {
+            const uint32_t* gate = p == 0 ? nullptr : flag + p - 1;
+            if (v.n_tets > 0)
+                hipLaunchKernelGGL(k_cc_hook, dim3(gt), dim3(kBlock), 0, s, v, f, gate, flag + p);
+            if (v.n_nodes > 0)
+                hipLaunchKernelGGL(k_cc_shortcut, dim3(gn), dim3(kBlock), 0, s, v.n_nodes, f, gate);
+            e = hipGetLastError();
         }
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_cc_finish, dim3(gf), dim3(kBlock), 0, s, v, f, mark, label, flag + kCountWord,
+                               flag + kTruncWord);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess)
+            e = finish_batch(flag, host_flag, kVertexBatch, passes, converged, s);
     }
     if (e == hipSuccess)
-        e = hipMemsetAsync(flag + 1, 0, sizeof(uint32_t), s);
-    if (e == hipSuccess && v.n_tets > 0) {
-        hipLaunchKernelGGL(k_cc_label, dim3(blocks(v.n_tets)), dim3(kBlock), 0, s, v, f, label, mark);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess && v.n_nodes > 0) {
-        hipLaunchKernelGGL(k_cc_count, dim3(gn), dim3(kBlock), 0, s, v.n_nodes, f, mark, flag);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(host_flag, flag + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(s);
-    if (e == hipSuccess)
-        *n_components = *host_flag;
+        *n_components = host_flag[kCountWord];
     return e;
 }
 
@@ -422,7 +439,7 @@ extern "C" sta_status sta_components(sta_ctx* ctx, int32_t* labels_dev, int64_t*
     hipError_t e = hipSuccess;
     if (!ctx->cc_ws) {
         void* q = nullptr;
-        e = hipMalloc(&q, sizeof(int32_t) * 2 * n + 256);  // parent and mark per vertex, 2 flags
+        e = hipMalloc(&q, sizeof(int32_t) * (2 * n + kFlagWords));  // parent and mark per vertex, the flags
         if (e != hipSuccess) {
             ctx->errmsg = std::string("connectivity workspace: ") + hipGetErrorString(e);
             return STA_ENOMEM;
@@ -431,7 +448,7 @@ extern "C" sta_status sta_components(sta_ctx* ctx, int32_t* labels_dev, int64_t*
         ctx->cc_ws = static_cast<int32_t*>(q);
     }
     if (!ctx->cc_host) {
-        e = hipHostMalloc((void**)&ctx->cc_host, sizeof(uint32_t), hipHostMallocDefault);
+        e = hipHostMalloc((void**)&ctx->cc_host, sizeof(uint32_t) * kFlagWords, hipHostMallocDefault);
         if (e != hipSuccess) {
             ctx->cc_host = nullptr;
             ctx->errmsg = std::string("connectivity host flag: ") + hipGetErrorString(e);
@@ -473,7 +490,7 @@ extern "C" sta_status sta_face_components(sta_ctx* ctx, int32_t* labels_dev, int
         }
         const std::vector<int2> pairs = host_face_pairs(T);
         void* q = nullptr;
-        const size_t bytes = sizeof(int32_t) * ((size_t)ctx->n_tets + 2) + sizeof(int2) * (pairs.size() + 1);
+        const size_t bytes = sizeof(int32_t) * ((size_t)ctx->n_tets + kFlagWords) + sizeof(int2) * (pairs.size() + 1);
         e = hipMalloc(&q, bytes);
         if (e != hipSuccess) {
             ctx->errmsg = std::string("face connectivity workspace: ") + hipGetErrorString(e);
@@ -481,7 +498,7 @@ extern "C" sta_status sta_face_components(sta_ctx* ctx, int32_t* labels_dev, int
         }
         ctx->owned.push_back(q);
         int32_t* base = static_cast<int32_t*>(q);
-        int2* pd = reinterpret_cast<int2*>(base + ((ctx->n_tets + 2 + 1) / 2) * 2);  // 8-byte aligned after f and flags
+        int2* pd = reinterpret_cast<int2*>(base + ((ctx->n_tets + kFlagWords + 1) / 2) * 2);  // 8-byte aligned after f and flags
         if (!pairs.empty())
             e = hipMemcpy(pd, pairs.data(), sizeof(int2) * pairs.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
@@ -493,7 +510,7 @@ extern "C" sta_status sta_face_components(sta_ctx* ctx, int32_t* labels_dev, int
         ctx->ccf_npairs = (int64_t)pairs.size();
     }
     if (!ctx->cc_host) {
-        e = hipHostMalloc((void**)&ctx->cc_host, sizeof(uint32_t), hipHostMallocDefault);
+        e = hipHostMalloc((void**)&ctx->cc_host, sizeof(uint32_t) * kFlagWords, hipHostMallocDefault);
         if (e != hipSuccess) {
             ctx->cc_host = nullptr;
             ctx->errmsg = std::string("connectivity host flag: ") + hipGetErrorString(e);

@@ -266,10 +266,10 @@ struct sta_ctx {
     bool tet_ml_stale = true;
     double* euler_ws = nullptr;     // implicit Euler: M_t, right-hand side, new u (3 x n_rows)
     double* audit_ws = nullptr;     // audit: nnz re-summed values, then 2 counters
-    int32_t* cc_ws = nullptr;       // connectivity: parent and mark per node, 2 flags
-    uint32_t* cc_host = nullptr;    // pinned flag read back after each pass
+    int32_t* cc_ws = nullptr;       // connectivity: parent and mark per node, then the pass flags
+    uint32_t* cc_host = nullptr;    // pinned copy of the pass flags, read back once per batch of passes
     int cc_passes = 0;              // passes of the last sta_components / sta_face_components
-    int32_t* ccf_ws = nullptr;      // face connectivity: parent per tet, 2 flags, then the face pairs
+    int32_t* ccf_ws = nullptr;      // face connectivity: parent per tet, the pass flags, then the face pairs
     int2* ccf_pairs = nullptr;      // candidate tet pairs with a common face
     int64_t ccf_npairs = 0;
     // batch layout: per mesh node / tet / value offsets (k+1 entries)
