@@ -181,8 +181,8 @@ def _traffic():
 def load_traffic(workload, kernels, per=None):
     """HBM bytes (FETCH_SIZE + WRITE_SIZE, scaled) from the committed rocprofv3 counter runs
     of `workload`: the kernels' summed bytes per unit, a unit being one dispatch of `per`
-    (default: of the first kernel).  None if a kernel has no record or the kernel sources
-    changed since the counters were taken."""
+    (default: of the first kernel).  None if a kernel has no record or the library's device
+    code changed since the counters were taken."""
     rec = _traffic().get("workloads", {}).get(workload, {}).get("kernels", {})
     if not all(k in rec for k in kernels) or (per is not None and per not in rec):
         return None
@@ -1044,11 +1044,11 @@ def connectivity_section(torch, stafem, w, frames, args):
                     "us_per_frame_at_period": round(med / period, 3)}
         if adj == "vertex" or n_pairs:
             nb = bytes_connectivity_pass(w.n_tets, w.n_nodes, n_pairs if adj == "face" else 0)
-            ks = (["k_cc_seed", "k_cc_shortcut", "k_cc_hook", "k_cc_label", "k_cc_count"] if adj == "vertex"
+            # the first kernel runs once per rebuild: the unit of the counted bytes
+            ks = (["k_cc_seed", "k_cc_shortcut", "k_cc_hook", "k_cc_finish"] if adj == "vertex"
                   else ["k_ccf_init", "k_ccf_seed", "k_ccf_hook", "k_cc_shortcut", "k_ccf_label"])
             out[adj]["roofline"] = roofline(f"connectivity ({adj}), one-pass lower bound", nb, med * 1e-6, 1,
-                                            traffic=load_traffic(f"connectivity_{adj}", ks, per=ks[3 if adj == "vertex"
-                                                                                                      else 4]))
+                                            traffic=load_traffic(f"connectivity_{adj}", ks, per=ks[0]))
         if adj in oracle_s:
             out[adj]["cpu_baseline"] = {"value": round(oracle_s[adj] * 1e6, 1), "unit": "us per rebuild",
                                         "cores": 1, "kind": "oracle",
