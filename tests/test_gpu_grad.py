@@ -28,6 +28,10 @@ def S():
     return stafem
 
 
+def bits(a):
+    return np.ascontiguousarray(a, dtype=np.float64).view(np.uint64)
+
+
 def small_case(seed=0):
     w = W.make_fracture(seed=seed, n=5, counts=[20, 40, 30])
     mask = w.mask_after(2)
@@ -275,3 +279,32 @@ def test_autograd_compliance_matches_adjoint():
     assert np.array_equal(logE.grad.cpu().numpy().view(np.uint64), gl.cpu().numpy().view(np.uint64))
     assert np.array_equal(x.grad.cpu().numpy().view(np.uint64), gx.cpu().numpy().view(np.uint64))
     asm.close()
+
+
+def test_batch_adjoint_equals_each_mesh_alone():
+    """The adjoint of a batched context, whose meshes' tet ranges do not fall on the element
+    pass's chunk boundaries (and whose chunks are ordered per mesh), equals each mesh's own
+    adjoint bit for bit after a few frames of every mesh's stream."""
+    Sm = S()
+    ws = W.make_batch(seed=4, count=5, frames=6, sizes=[2, 5, 3, 1, 4])
+    b = Sm.Batch.from_workloads(ws)
+    off = b.offsets()
+    assert any(int(t) % 16 for t in off["tet"][1:-1])
+    singles = [Sm.Assembler.from_workload(w) for w in ws]
+    for t in range(4):
+        gi = np.concatenate([w.frames[t][0].astype(np.int64) + off["tet"][j] for j, w in enumerate(ws)])
+        gs = np.concatenate([w.frames[t][1] for w in ws])
+        b.apply_edits(*Sm.upload_frame(gi.astype(np.int32), gs.astype(np.uint8)))
+        for a, w in zip(singles, ws):
+            a.apply_edits(*Sm.upload_frame(*w.frames[t]))
+    rng = np.random.default_rng(11)
+    g = rng.standard_normal(b.nnz)
+    gl, gx = b.adjoint(torch.from_numpy(g).cuda())
+    gl, gx = gl.cpu().numpy(), gx.cpu().numpy().reshape(-1)
+    for j, a in enumerate(singles):
+        sl, sx = a.adjoint(torch.from_numpy(g[off["nnz"][j]:off["nnz"][j + 1]].copy()).cuda())
+        assert np.array_equal(bits(gl[off["tet"][j]:off["tet"][j + 1]]), bits(sl.cpu().numpy())), j
+        assert np.array_equal(bits(gx[3 * off["node"][j]:3 * off["node"][j + 1]]), bits(sx.cpu().numpy().reshape(-1))), j
+        a.close()
+    assert b.status_sync() == Sm.STA_OK
+    b.close()
