@@ -282,7 +282,8 @@ sta_status sta_euler_step(sta_ctx* ctx, double* u_dev, double* v_dev, const doub
  * int32) receives, per tet, its component's smallest vertex id, or -1 for an
  * inactive tet; labels do not depend on execution order.  *n_components
  * (may be NULL) receives the number of components.  Synchronises `stream`
- * (the host checks convergence after each pass). */
+ * (the host reads the convergence flags and the count once per batch of
+ * passes, normally once per call). */
 sta_status sta_components(sta_ctx* ctx, int32_t* labels_dev, int64_t* n_components, void* stream);
 
 /* Connectivity over shared faces (Sec. 3.6 leaves the adjacency open; this
