@@ -102,13 +102,26 @@ def test_trace_writes_one_line_per_call_with_frame_stats(tmp_path):
         asm.apply_edits(*Sm.upload_frame(ids, st))
         d = asm.last_frame_stats()
         want.append({k: d[k] for k in Sm.Assembler.FRAME_STATS})
+    # the device-count entry point (a buffer of capacity 1024) and the +/- delta policy
+    (i0, s0), (i1, s1) = W.merge_stream(w.frames)[:2]
+    cap = 1024
+    bi = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    bs = torch.zeros(cap, dtype=torch.uint8, device="cuda")
+    bi[:len(i0)].copy_(torch.from_numpy(i0.astype(np.int32)))
+    bs[:len(i0)].copy_(torch.from_numpy(s0.astype(np.uint8)))
+    asm.apply_edits_dev(bi, bs, torch.tensor([len(i0)], dtype=torch.int32, device="cuda"))
+    asm.apply_edits_delta(*Sm.upload_frame(i1, s1))
     asm.full_rebuild()
     asm.close()
     lines = [json.loads(l) for l in path.read_text().splitlines()]
-    assert [l["seq"] for l in lines] == list(range(len(w.frames) + 1))
-    assert [l["call"] for l in lines] == ["apply_edits"] * len(w.frames) + ["full_rebuild"]
+    nf = len(w.frames)
+    assert [l["seq"] for l in lines] == list(range(nf + 3))
+    assert [l["call"] for l in lines] == ["apply_edits"] * nf + ["apply_edits_dev", "apply_edits_delta", "full_rebuild"]
     for l, (ids, _), s in zip(lines, w.frames, want):
         assert l["edits"] == len(ids) and l["stats"] == s and l["stats"]["edits"] == len(ids)
+    assert lines[nf]["capacity"] == cap and lines[nf]["stats"]["edits"] == len(i0)
+    assert lines[nf + 1]["edits"] == len(i1) and lines[nf + 1]["stats"]["edits"] == len(i1)
+    assert lines[nf + 1]["stats"]["diag_blocks"] == 0  # the delta policy claims no blocks
     assert "stats" not in lines[-1]
     assert all(a["host_us"] <= b["host_us"] for a, b in zip(lines, lines[1:]))
     # a context built without STA_TRACE writes nothing more
