@@ -393,11 +393,19 @@ class Stream:
         eb = bytes_element(float(np.mean(act)), self.n_tets, self.n_nodes)
         n_e, ms_e = kt.get("element", (0, 0.0))
         n_r, ms_r = kt.get("reduce", (0, 0.0))
-        return {"element": roofline("k_element", eb * n_e, ms_e * 1e-3, n_e,
-                                    traffic=load_traffic(self.workload, [kernel_instance(asm, "k_element")])),
-                "reduce": roofline("k_reduce_all", rb * n_r, ms_r * 1e-3, n_r,
-                                   traffic=load_traffic(self.workload, [kernel_instance(asm, "k_reduce_all")])),
-                "rebuild_us_mean": round((ms_e + ms_r) * 1e3 / max(n_r, 1), 3),
+        # a batch too large for the Infinity Cache is rebuilt in mesh groups (one element and two
+        # reduce launches per group): rates and counted bytes are per rebuild, all groups together
+        rebuilds = len(self.frames_host) * reps
+        per_e, per_r = n_e / max(rebuilds, 1), n_r / max(rebuilds, 1)
+        te = load_traffic(self.workload, [kernel_instance(asm, "k_element")])
+        tr = load_traffic(self.workload, [kernel_instance(asm, "k_reduce_all")])
+        el = roofline("k_element", eb * rebuilds, ms_e * 1e-3, rebuilds,
+                      traffic=None if te is None else round(te * per_e, 1))
+        re = roofline("k_reduce_all", rb * rebuilds, ms_r * 1e-3, rebuilds,
+                      traffic=None if tr is None else round(tr * per_r, 1))
+        el["launches_per_rebuild"], re["launches_per_rebuild"] = per_e, per_r
+        return {"element": el, "reduce": re,
+                "rebuild_us_mean": round((ms_e + ms_r) * 1e3 / max(rebuilds, 1), 3),
                 "full_rebuild_alg_bytes": int(eb + rb)}
 
     def mask_before(self, k):

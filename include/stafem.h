@@ -200,6 +200,9 @@ sta_status sta_last_frame_stats(sta_ctx* ctx, void* stream, int64_t* out, int n_
  * file that cannot be opened for appending fails the build with STA_EINVAL. */
 #define STA_KERNEL_ELEMENT 0   /* element contributions (rebuild / activation) */
 #define STA_KERNEL_REDUCE 1    /* re-sum of every block (rebuild) */
+/* A batch whose contributions exceed 200 MB is rebuilt in groups of
+ * consecutive meshes: each group counts one STA_KERNEL_ELEMENT launch and two
+ * STA_KERNEL_REDUCE launches (diagonal, then off-diagonal blocks). */
 #define STA_KERNEL_EDITS 2     /* streaming phase 1: validate, flip, claim */
 #define STA_KERNEL_TOUCHED 3   /* streaming phase 2: re-sum claimed blocks */
 #define STA_KERNEL_ADJOINT 4

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstddef>
 #include <cstdio>
 #include <cstdint>
@@ -274,6 +275,9 @@ struct sta_ctx {
     int64_t ccf_npairs = 0;
     // batch layout: per mesh node / tet / value offsets (k+1 entries)
     std::vector<int64_t> node_off, tet_off, nnz_off;
+    // A batch rebuilt in groups of consecutive meshes (empty: in one pass): per group its tet
+    // range, its diagonal block range and its off-diagonal block range, each [begin, end).
+    std::vector<std::array<int64_t, 6>> rebuild_groups;
     std::string errmsg;
     // per-kernel event timing
     bool timing = false;

@@ -140,6 +140,14 @@ def test_batch_full_size():
     ws = W.make_batch(seed=0)
     b, masks = run_batch(ws, {0, 6, 12, 18, 23}, 1, 1, "batch 64")
     vals = host_values(b)
+    # its 853 MB of contributions make the rebuild run in mesh groups: same bits as the stream
+    b.enable_kernel_timing(True)
+    b.kernel_times()
+    b.full_rebuild()
+    kt = b.kernel_times()
+    b.enable_kernel_timing(False)
+    assert kt["element"][0] > 1 and kt["reduce"][0] == 2 * kt["element"][0], kt
+    check(host_values(b), vals, "grouped rebuild vs stream")
     off = b.offsets()
     for j in (0, 17, 40, 63):
         a = Sm.Assembler.from_workload(ws[j])
