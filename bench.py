@@ -1164,7 +1164,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=48, help="oracle rebuilds in the CPU baseline sample")
     ap.add_argument("--quick", action="store_true",
                     help="headline timed steps, 3 rebuilds and a 512 MiB reference copy only (for profiler runs)")
-    ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
+    ap.add_argument("--detail", default="bench_detail.json",
                     help="file for the full report (per-frame rows, autotuner report, every section)")
     args = ap.parse_args()
 
